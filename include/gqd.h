@@ -1,0 +1,153 @@
+/* gqd: implicit, exactly unitary geometric integrators for nonadiabatic quantum
+ * dynamics in the adiabatic representation, on AMD Instinct MI355X (gfx950), FP64.
+ *
+ * Method: S. Choi and J. Vanicek, "Efficient geometric integrators for nonadiabatic
+ * quantum dynamics. I. The adiabatic representation", J. Chem. Phys. 150, 204112
+ * (2019), arXiv:1902.04661.  Atomic units with hbar = 1 (the paper's App. A).
+ *
+ * Problem.  A batch of independent wavepackets ("items").  Item b is an S = 2
+ * component wavefunction on a uniform periodic grid of n_b points on [qmin_b, qmax_b)
+ * (right end excluded, dq = L/n, L = qmax - qmin), with
+ *   H = (1/2m) [p 1 - i F(q)]^dag [p 1 - i F(q)] + V(q)                   (Eq. 22)
+ * where V = diag(V_1, V_2) (adiabatic surfaces) and F is the antisymmetric
+ * nonadiabatic coupling, F12 = -F21, F11 = F22 = 0 (Eq. 28).  p acts by the dynamic
+ * Fourier method (Sec. II.E): forward DFT sum_j x_j exp(-2 pi i j k/n), multiply by
+ * p_k = 2 pi k'/L with k' = k for k < n/2 and k - n otherwise, inverse DFT with 1/n.
+ *
+ * Memory.  Every buffer argument is a DEVICE pointer owned by the caller (for example
+ * torch tensors); the library never frees them and keeps only the V and F pointers
+ * given to gqd_set_surfaces, which must stay valid while the handle uses them.
+ * Layouts, items concatenated in batch order:
+ *   psi  complex128 (interleaved re, im) [item][surface 2][n_b]      ("state vector")
+ *   V    float64 [item][surface 2][n_b]
+ *   F    float64 [item][n_b]           (F12 along q)
+ *   gF   float64 [item][n_b]           (gradient with respect to F12)
+ * gqd_state_offset() gives each item's offset in complex elements; V uses the same
+ * offsets in doubles; F and gF use half of it.
+ *
+ * Streams and errors.  Calls are asynchronous on the given hipStream_t (NULL = the
+ * null stream) unless they take a gqd_stats pointer that is not NULL: then the call
+ * waits for its own work and reports GMRES failures through its return value.
+ * Every call returns a gqd_status; on failure gqd_last_error() (thread-local) holds
+ * a message.  Nothing throws across this interface.
+ */
+#ifndef GQD_H
+#define GQD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GQD_OK = 0,
+  GQD_ERR_INVALID = -1,       /* bad argument (null pointer, size, option) */
+  GQD_ERR_HIP = -2,           /* a HIP runtime call failed */
+  GQD_ERR_NOMEM = -3,         /* a host or small device table could not be allocated */
+  GQD_ERR_NOT_CONVERGED = -4, /* some GMRES solve hit maxit (Sec. III: large steps stall GMRES) */
+  GQD_ERR_UNSUPPORTED = -5,   /* grid size or dimensionality without a kernel */
+  GQD_ERR_NONFINITE = -6,     /* a norm became NaN or Inf; that item stopped there */
+  GQD_ERR_STATE = -7          /* surfaces or workspace not set */
+} gqd_status;
+
+/* Base second-order method (Sec. II.C). */
+typedef enum {
+  GQD_TRAP = 0, /* trapezoidal rule, U_impl(h/2) U_expl(h/2), Eq. (18) */
+  GQD_MIDP = 1  /* implicit midpoint, U_expl(h/2) U_impl(h/2), Eq. (19) */
+} gqd_method;
+
+/* Recursive symmetric composition (Sec. II.D). */
+typedef enum {
+  GQD_TRIPLE_JUMP = 0, /* M = 3, Eq. (20) */
+  GQD_SUZUKI = 1       /* M = 5, Eq. (21) */
+} gqd_scheme;
+
+typedef struct {
+  int dims;           /* D: number of nuclear degrees of freedom; must be 1 */
+  int surfaces;       /* S: must be 2 */
+  int batch;          /* number of items, >= 1 */
+  const int* n;       /* host [batch*dims]: grid points, each one of 256, 512, 1024, 2048, 4096 */
+  const double* qmin; /* host [batch*dims] */
+  const double* qmax; /* host [batch*dims], > qmin */
+  const double* mass; /* host [dims], > 0 */
+} gqd_grid_desc;
+
+typedef struct {
+  double tol;  /* GMRES stops when its residual estimate <= tol * ||b|| (Euclidean); > 0 */
+  int restart; /* Krylov dimension m before a restart, 1..64 */
+  int maxit;   /* Arnoldi iterations allowed per solve, >= 1 */
+  int literal; /* 1: perform every explicit half-step (3 + I H-applications per substep,
+                  Table I); 0: use the Cayley identities (midpoint psi' = 2x - psi,
+                  trapezoid reuses H psi' = (b - psi')/(i a)), 2 + I per substep */
+} gqd_solver_opts;
+
+typedef struct {
+  long long h_applies;  /* H applications, all items */
+  long long iterations; /* Arnoldi iterations, all items */
+  long long solves;     /* GMRES solves, all items */
+  int max_iters;        /* largest iteration count of one solve */
+  int failures;         /* solves that hit maxit */
+  int failed_item;      /* first item with a failure or non-finite norm, else -1 */
+  int nonfinite;        /* items stopped by a non-finite norm */
+} gqd_stats;
+
+typedef struct gqd_handle gqd_handle;
+
+/* Builds host plans and small device tables (item descriptors, twiddles, per-item
+ * counters).  The handle owns those tables and frees them in gqd_destroy. */
+gqd_status gqd_create(gqd_handle** h, const gqd_grid_desc* g);
+void gqd_destroy(gqd_handle* h);
+
+/* Total complex elements of one state vector (all items), and item b's offset. */
+gqd_status gqd_state_size(const gqd_handle* h, long long* n_complex);
+gqd_status gqd_state_offset(const gqd_handle* h, int item, long long* offset);
+
+/* Workspace for the solver: (restart + 5) state vectors.  The caller allocates it
+ * (bytes from gqd_workspace_size) and passes it once; it must stay valid. */
+gqd_status gqd_workspace_size(const gqd_handle* h, const gqd_solver_opts* o, size_t* bytes);
+gqd_status gqd_set_workspace(gqd_handle* h, void* dev_ptr, size_t bytes);
+
+/* Adiabatic surfaces V and coupling F12 (device pointers, layouts above). */
+gqd_status gqd_set_surfaces(gqd_handle* h, const double* V, const double* F);
+
+/* psi_out = H psi_in (Eq. 22); psi_in and psi_out must not overlap. */
+gqd_status gqd_apply_H(gqd_handle* h, const void* psi_in, void* psi_out, void* stream);
+
+/* One base step of length dt in place: trapezoidal rule or implicit midpoint, each
+ * with its implicit half solved by GMRES from the explicit-Euler guess (Sec. II.C). */
+gqd_status gqd_implicit_step(gqd_handle* h, gqd_method m, double dt, void* psi,
+                             const gqd_solver_opts* o, gqd_stats* st, void* stream);
+
+/* nsteps steps of length dt in place, each the recursive symmetric composition of the
+ * base method to the given even order (2, 4, 6, 8, 10): 3^(order/2-1) triple-jump or
+ * 5^(order/2-1) Suzuki substeps, gamma_1 applied first (Sec. II.D).  dt may be
+ * negative (backward propagation). */
+gqd_status gqd_propagate(gqd_handle* h, gqd_method m, gqd_scheme s, int order, double dt,
+                         long long nsteps, void* psi, const gqd_solver_opts* o,
+                         gqd_stats* st, void* stream);
+
+/* Reverse sweep of gqd_propagate for a real loss L(psi(T)), with no stored
+ * trajectory: every substep's Cayley map is inverted exactly (time reversibility,
+ * App. A, Eq. A40).  On entry psi holds psi(T) and lambda holds dL/dpsi*(T) in the
+ * Euclidean sense (dL = 2 Re sum conj(lambda) dpsi); on return psi holds the
+ * reconstructed psi(0), lambda holds dL/dpsi*(0), and dL/dF12 on the grid has been
+ * ADDED to gF.  The same sweep serves both base methods (they share the Cayley map). */
+gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme s, int order, double dt, long long nsteps,
+                       void* psi, void* lambda, double* gF, const gqd_solver_opts* o,
+                       gqd_stats* st, void* stream);
+
+/* Per item: out[4b..4b+3] = (||psi||, <psi|H|psi>, P_1, P_2) with the grid inner product
+ * <a|b> = dq sum conj(a) b (Sec. II.A, Eq. 6).  out: device float64 [batch*4]. */
+gqd_status gqd_diag(gqd_handle* h, const void* psi, double* out, void* stream);
+
+/* Per item: out[2b], out[2b+1] = Re, Im <psi|phi>.  out: device float64 [batch*2]. */
+gqd_status gqd_inner(gqd_handle* h, const void* psi, const void* phi, double* out, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* gqd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GQD_H */

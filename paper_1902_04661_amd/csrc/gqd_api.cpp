@@ -1,0 +1,419 @@
+// Host side of the gqd C ABI: validation, item planning, twiddle table, launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gqd.h"
+#include "gqd_internal.h"
+
+using namespace gqd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gqd_status fail(gqd_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+gqd_status hip_fail(hipError_t e, const char* what) {
+  return fail(GQD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define GQD_HIP(call)                                 \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+int class_of(int n) {
+  for (int c = 0; c < kNumClasses; ++c)
+    if (kClassN[c] == n) return c;
+  return -1;
+}
+
+constexpr size_t kLdsMax = 160 * 1024;
+
+}  // namespace
+
+struct gqd_handle {
+  int batch = 0;
+  double mass = 0.0;
+  std::vector<ItemMeta> items;
+  long long total_complex = 0;
+  std::vector<int> class_lists[kNumClasses];
+  ItemMeta* d_items = nullptr;
+  int* d_lists[kNumClasses] = {};
+  double2* d_tw = nullptr;
+  ItemStats* d_stats = nullptr;
+  std::vector<ItemStats> h_stats;
+  const double* V = nullptr;
+  const double* F = nullptr;
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  hipStream_t side[kNumClasses] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kNumClasses] = {};
+  bool streams_ready = false;
+};
+
+namespace {
+
+gqd_status check_opts(const gqd_handle* h, const gqd_solver_opts* o) {
+  if (!o) return fail(GQD_ERR_INVALID, "solver options are NULL");
+  if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(GQD_ERR_INVALID, "tol must be finite and > 0");
+  if (o->restart < 1 || o->restart > kMaxRestart) return fail(GQD_ERR_INVALID, "restart must be in 1..64");
+  if (o->maxit < 1) return fail(GQD_ERR_INVALID, "maxit must be >= 1");
+  for (int c = 0; c < kNumClasses; ++c) {
+    if (!h->class_lists[c].empty() && lds_bytes(kClassN[c], o->restart) > kLdsMax)
+      return fail(GQD_ERR_UNSUPPORTED, "restart " + std::to_string(o->restart) +
+                                           " needs more than 160 KB of LDS at n = " +
+                                           std::to_string(kClassN[c]));
+  }
+  return GQD_OK;
+}
+
+size_t work_need(const gqd_handle* h, int m) {
+  return (size_t)h->total_complex * (size_t)(m + kWorkExtra) * sizeof(double2);
+}
+
+gqd_status ensure_streams(gqd_handle* h) {
+  if (h->streams_ready) return GQD_OK;
+  GQD_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+  for (int c = 0; c < kNumClasses; ++c) {
+    GQD_HIP(hipStreamCreateWithFlags(&h->side[c], hipStreamNonBlocking));
+    GQD_HIP(hipEventCreateWithFlags(&h->ev_join[c], hipEventDisableTiming));
+  }
+  h->streams_ready = true;
+  return GQD_OK;
+}
+
+// Launch `fn` once per non-empty size class.  Several classes run concurrently on
+// side streams forked from and joined back into the caller's stream.
+template <class Fn>
+gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
+  int active = 0;
+  for (int c = 0; c < kNumClasses; ++c) active += h->class_lists[c].empty() ? 0 : 1;
+  if (active == 1) {
+    for (int c = 0; c < kNumClasses; ++c) {
+      if (h->class_lists[c].empty()) continue;
+      a.list = h->d_lists[c];
+      a.nlist = (int)h->class_lists[c].size();
+      GQD_HIP(fn(c, a, stream));
+    }
+    return GQD_OK;
+  }
+  gqd_status st = ensure_streams(h);
+  if (st != GQD_OK) return st;
+  GQD_HIP(hipEventRecord(h->ev_fork, stream));
+  for (int c = 0; c < kNumClasses; ++c) {
+    if (h->class_lists[c].empty()) continue;
+    GQD_HIP(hipStreamWaitEvent(h->side[c], h->ev_fork, 0));
+    a.list = h->d_lists[c];
+    a.nlist = (int)h->class_lists[c].size();
+    GQD_HIP(fn(c, a, h->side[c]));
+    GQD_HIP(hipEventRecord(h->ev_join[c], h->side[c]));
+    GQD_HIP(hipStreamWaitEvent(stream, h->ev_join[c], 0));
+  }
+  return GQD_OK;
+}
+
+KArgs base_args(const gqd_handle* h) {
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.items = h->d_items;
+  a.V = h->V;
+  a.F = h->F;
+  a.tw = h->d_tw;
+  a.inv2m = 1.0 / (2.0 * h->mass);
+  a.mass = h->mass;
+  a.stats = h->d_stats;
+  return a;
+}
+
+gqd_status make_gammas(gqd_scheme s, int order, GammaTab* gt) {
+  if (order < 2 || order % 2 || order > 2 * (kMaxLevels + 1))
+    return fail(GQD_ERR_INVALID, "order must be even, 2..10");
+  if (s != GQD_TRIPLE_JUMP && s != GQD_SUZUKI) return fail(GQD_ERR_INVALID, "unknown composition scheme");
+  std::memset(gt, 0, sizeof(*gt));
+  gt->arity = (s == GQD_TRIPLE_JUMP) ? 3 : 5;
+  gt->levels = order / 2 - 1;
+  gt->count = 1;
+  for (int l = 0; l < gt->levels; ++l) {
+    const int p = 2 * l + 2;  // order of the method being composed
+    if (s == GQD_TRIPLE_JUMP) {
+      const double r = std::pow(2.0, 1.0 / (p + 1));
+      gt->side[l] = 1.0 / (2.0 - r);
+      gt->mid[l] = -r / (2.0 - r);
+    } else {
+      const double r = std::pow(4.0, 1.0 / (p + 1));
+      gt->side[l] = 1.0 / (4.0 - r);
+      gt->mid[l] = -r / (4.0 - r);
+    }
+    gt->count *= gt->arity;
+  }
+  return GQD_OK;
+}
+
+gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
+  GQD_HIP(hipStreamSynchronize(stream));
+  GQD_HIP(hipMemcpy(h->h_stats.data(), h->d_stats, sizeof(ItemStats) * h->batch, hipMemcpyDeviceToHost));
+  std::memset(st, 0, sizeof(*st));
+  st->failed_item = -1;
+  for (int b = 0; b < h->batch; ++b) {
+    const ItemStats& s = h->h_stats[b];
+    st->h_applies += s.h_applies;
+    st->iterations += s.iterations;
+    st->solves += s.solves;
+    if (s.max_iters > st->max_iters) st->max_iters = s.max_iters;
+    st->failures += s.failures;
+    st->nonfinite += s.nonfinite;
+    if ((s.failures || s.nonfinite) && st->failed_item < 0) st->failed_item = b;
+  }
+  if (st->nonfinite) return fail(GQD_ERR_NONFINITE, "a norm became non-finite (first item " +
+                                                         std::to_string(st->failed_item) + ")");
+  if (st->failures) return fail(GQD_ERR_NOT_CONVERGED, "GMRES hit maxit in " + std::to_string(st->failures) +
+                                                           " solves (first item " +
+                                                           std::to_string(st->failed_item) + ")");
+  return GQD_OK;
+}
+
+gqd_status ready(const gqd_handle* h, bool need_work, const gqd_solver_opts* o) {
+  if (!h) return fail(GQD_ERR_INVALID, "handle is NULL");
+  if (!h->V || !h->F) return fail(GQD_ERR_STATE, "surfaces not set (gqd_set_surfaces)");
+  if (need_work) {
+    gqd_status s = check_opts(h, o);
+    if (s != GQD_OK) return s;
+    if (!h->work) return fail(GQD_ERR_STATE, "workspace not set (gqd_set_workspace)");
+    if (h->work_bytes < work_need(h, o->restart))
+      return fail(GQD_ERR_STATE, "workspace too small for this restart length");
+  }
+  return GQD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gqd_last_error(void) { return g_last_error.c_str(); }
+
+gqd_status gqd_create(gqd_handle** out, const gqd_grid_desc* g) {
+  if (!out || !g) return fail(GQD_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  if (g->dims != 1) return fail(GQD_ERR_UNSUPPORTED, "only dims = 1 is supported");
+  if (g->surfaces != 2) return fail(GQD_ERR_UNSUPPORTED, "only surfaces = 2 is supported");
+  if (g->batch < 1) return fail(GQD_ERR_INVALID, "batch must be >= 1");
+  if (!g->n || !g->qmin || !g->qmax || !g->mass) return fail(GQD_ERR_INVALID, "NULL grid array");
+  if (!(g->mass[0] > 0.0) || !std::isfinite(g->mass[0])) return fail(GQD_ERR_INVALID, "mass must be > 0");
+  gqd_handle* h = new (std::nothrow) gqd_handle();
+  if (!h) return fail(GQD_ERR_NOMEM, "out of host memory");
+  h->batch = g->batch;
+  h->mass = g->mass[0];
+  h->items.resize(g->batch);
+  long long off = 0;
+  for (int b = 0; b < g->batch; ++b) {
+    const int n = g->n[b];
+    const int cls = class_of(n);
+    const double L = g->qmax[b] - g->qmin[b];
+    if (cls < 0) {
+      delete h;
+      return fail(GQD_ERR_UNSUPPORTED, "item " + std::to_string(b) + ": n = " + std::to_string(n) +
+                                           " (supported: 256, 512, 1024, 2048, 4096)");
+    }
+    if (!(L > 0.0) || !std::isfinite(L)) {
+      delete h;
+      return fail(GQD_ERR_INVALID, "item " + std::to_string(b) + ": qmax must exceed qmin");
+    }
+    ItemMeta& m = h->items[b];
+    m.n = n;
+    m.cls = cls;
+    m.off = off;
+    m.voff = off;
+    m.foff = off / 2;
+    m.dq = L / n;
+    m.pscale = 2.0 * M_PI / L;
+    off += 2LL * n;
+    h->class_lists[cls].push_back(b);
+  }
+  h->total_complex = off;
+  h->h_stats.resize(g->batch);
+  auto cleanup = [&](gqd_status s) {
+    gqd_destroy(h);
+    return s;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&h->d_items, sizeof(ItemMeta) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc items"));
+  if ((e = hipMemcpy(h->d_items, h->items.data(), sizeof(ItemMeta) * g->batch, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemcpy items"));
+  for (int c = 0; c < kNumClasses; ++c) {
+    if (h->class_lists[c].empty()) continue;
+    const size_t bytes = sizeof(int) * h->class_lists[c].size();
+    if ((e = hipMalloc(&h->d_lists[c], bytes)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc lists"));
+    if ((e = hipMemcpy(h->d_lists[c], h->class_lists[c].data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMemcpy lists"));
+  }
+  // twiddles exp(-2 pi i k / 4096), evaluated in extended precision and rounded once
+  std::vector<double2> tw(kTwiddleN);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < kTwiddleN; ++k) {
+    const long double ang = 2.0L * pi * (long double)k / (long double)kTwiddleN;
+    tw[k] = make_double2((double)cosl(ang), (double)-sinl(ang));
+  }
+  if ((e = hipMalloc(&h->d_tw, sizeof(double2) * kTwiddleN)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc twiddles"));
+  if ((e = hipMemcpy(h->d_tw, tw.data(), sizeof(double2) * kTwiddleN, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemcpy twiddles"));
+  if ((e = hipMalloc(&h->d_stats, sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc stats"));
+  if ((e = hipMemset(h->d_stats, 0, sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMemset stats"));
+  if ((e = configure_kernels(kMaxRestart)) != hipSuccess) return cleanup(hip_fail(e, "configure kernels"));
+  *out = h;
+  return GQD_OK;
+}
+
+void gqd_destroy(gqd_handle* h) {
+  if (!h) return;
+  if (h->d_items) (void)hipFree(h->d_items);
+  for (int c = 0; c < kNumClasses; ++c)
+    if (h->d_lists[c]) (void)hipFree(h->d_lists[c]);
+  if (h->d_tw) (void)hipFree(h->d_tw);
+  if (h->d_stats) (void)hipFree(h->d_stats);
+  if (h->streams_ready) {
+    for (int c = 0; c < kNumClasses; ++c) {
+      (void)hipStreamDestroy(h->side[c]);
+      (void)hipEventDestroy(h->ev_join[c]);
+    }
+    (void)hipEventDestroy(h->ev_fork);
+  }
+  delete h;
+}
+
+gqd_status gqd_state_size(const gqd_handle* h, long long* n) {
+  if (!h || !n) return fail(GQD_ERR_INVALID, "NULL argument");
+  *n = h->total_complex;
+  return GQD_OK;
+}
+
+gqd_status gqd_state_offset(const gqd_handle* h, int item, long long* off) {
+  if (!h || !off) return fail(GQD_ERR_INVALID, "NULL argument");
+  if (item < 0 || item >= h->batch) return fail(GQD_ERR_INVALID, "item out of range");
+  *off = h->items[item].off;
+  return GQD_OK;
+}
+
+gqd_status gqd_workspace_size(const gqd_handle* h, const gqd_solver_opts* o, size_t* bytes) {
+  if (!h || !bytes) return fail(GQD_ERR_INVALID, "NULL argument");
+  gqd_status s = check_opts(h, o);
+  if (s != GQD_OK) return s;
+  *bytes = work_need(h, o->restart);
+  return GQD_OK;
+}
+
+gqd_status gqd_set_workspace(gqd_handle* h, void* p, size_t bytes) {
+  if (!h || !p) return fail(GQD_ERR_INVALID, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(p) & 15) != 0) return fail(GQD_ERR_INVALID, "workspace must be 16-byte aligned");
+  h->work = p;
+  h->work_bytes = bytes;
+  return GQD_OK;
+}
+
+gqd_status gqd_set_surfaces(gqd_handle* h, const double* V, const double* F) {
+  if (!h || !V || !F) return fail(GQD_ERR_INVALID, "NULL argument");
+  h->V = V;
+  h->F = F;
+  return GQD_OK;
+}
+
+gqd_status gqd_apply_H(gqd_handle* h, const void* in, void* out, void* stream) {
+  gqd_status s = ready(h, false, nullptr);
+  if (s != GQD_OK) return s;
+  if (!in || !out) return fail(GQD_ERR_INVALID, "NULL state pointer");
+  if (in == out) return fail(GQD_ERR_INVALID, "psi_in and psi_out must differ");
+  KArgs a = base_args(h);
+  a.psi = (double2*)in;
+  a.aux = (double2*)out;
+  return for_each_class(h, (hipStream_t)stream, a, launch_apply_h);
+}
+
+gqd_status gqd_propagate(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, double dt,
+                         long long nsteps, void* psi, const gqd_solver_opts* o, gqd_stats* st,
+                         void* stream) {
+  gqd_status s = ready(h, true, o);
+  if (s != GQD_OK) return s;
+  if (!psi) return fail(GQD_ERR_INVALID, "NULL state pointer");
+  if (m != GQD_TRAP && m != GQD_MIDP) return fail(GQD_ERR_INVALID, "unknown method");
+  if (!std::isfinite(dt)) return fail(GQD_ERR_INVALID, "dt must be finite");
+  if (nsteps < 0) return fail(GQD_ERR_INVALID, "nsteps must be >= 0");
+  KArgs a = base_args(h);
+  s = make_gammas(sch, order, &a.gt);
+  if (s != GQD_OK) return s;
+  a.psi = (double2*)psi;
+  a.work = (double2*)h->work;
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+  a.method = (m == GQD_TRAP) ? kTrap : kMidp;
+  a.dt = dt;
+  a.nsteps = nsteps;
+  a.hpsi_valid = 0;
+  hipStream_t strm = (hipStream_t)stream;
+  a.mode = 0;
+  s = for_each_class(h, strm, a, launch_run);
+  if (s != GQD_OK) return s;
+  return st ? collect_stats(h, strm, st) : GQD_OK;
+}
+
+gqd_status gqd_implicit_step(gqd_handle* h, gqd_method m, double dt, void* psi, const gqd_solver_opts* o,
+                             gqd_stats* st, void* stream) {
+  return gqd_propagate(h, m, GQD_SUZUKI, 2, dt, 1, psi, o, st, stream);
+}
+
+gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long long nsteps, void* psi,
+                       void* lambda, double* gF, const gqd_solver_opts* o, gqd_stats* st, void* stream) {
+  gqd_status s = ready(h, true, o);
+  if (s != GQD_OK) return s;
+  if (!psi || !lambda || !gF) return fail(GQD_ERR_INVALID, "NULL pointer");
+  if (!std::isfinite(dt)) return fail(GQD_ERR_INVALID, "dt must be finite");
+  if (nsteps < 0) return fail(GQD_ERR_INVALID, "nsteps must be >= 0");
+  KArgs a = base_args(h);
+  s = make_gammas(sch, order, &a.gt);
+  if (s != GQD_OK) return s;
+  a.psi = (double2*)psi;
+  a.aux = (double2*)lambda;
+  a.gF = gF;
+  a.work = (double2*)h->work;
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+  a.dt = dt;
+  a.nsteps = nsteps;
+  hipStream_t strm = (hipStream_t)stream;
+  a.mode = 1;
+  a.method = kMidp;
+  s = for_each_class(h, strm, a, launch_run);
+  if (s != GQD_OK) return s;
+  return st ? collect_stats(h, strm, st) : GQD_OK;
+}
+
+gqd_status gqd_diag(gqd_handle* h, const void* psi, double* out, void* stream) {
+  gqd_status s = ready(h, false, nullptr);
+  if (s != GQD_OK) return s;
+  if (!psi || !out) return fail(GQD_ERR_INVALID, "NULL pointer");
+  KArgs a = base_args(h);
+  a.psi = (double2*)psi;
+  a.out = out;
+  return for_each_class(h, (hipStream_t)stream, a, launch_diag);
+}
+
+gqd_status gqd_inner(gqd_handle* h, const void* psi, const void* phi, double* out, void* stream) {
+  gqd_status s = ready(h, false, nullptr);
+  if (s != GQD_OK) return s;
+  if (!psi || !phi || !out) return fail(GQD_ERR_INVALID, "NULL pointer");
+  KArgs a = base_args(h);
+  a.psi = (double2*)psi;
+  a.aux = (double2*)phi;
+  a.out = out;
+  return for_each_class(h, (hipStream_t)stream, a, launch_inner);
+}
+
+}  // extern "C"

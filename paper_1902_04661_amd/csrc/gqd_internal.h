@@ -1,0 +1,99 @@
+// Structures shared by the host API (gqd_api.cpp) and the kernels (gqd_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gqd {
+
+constexpr int kTwiddleN = 4096;  // twiddle table exp(-2 pi i k / 4096)
+constexpr int kMaxLevels = 4;  // compositions up to order 10
+constexpr int kMaxArity = 5;   // Suzuki fractal has 5 substeps per level
+constexpr int kMaxRestart = 64;
+// workspace per item: m + kWorkExtra state vectors (basis m+1, four slots, one parking slot)
+constexpr int kWorkExtra = 6;
+constexpr int kNumClasses = 5;  // N = 256, 512, 1024, 2048, 4096
+constexpr int kClassN[kNumClasses] = {256, 512, 1024, 2048, 4096};
+
+// Per-item description, resident on the device.
+struct ItemMeta {
+  int n;                // grid points (1D)
+  int cls;              // index into kClassN
+  long long off;        // offset of the item's state, in complex elements (= sum of 2n before it)
+  long long voff;       // offset into V (doubles), [2][n] per item
+  long long foff;       // offset into F (doubles), [n] per item
+  double dq;            // grid spacing
+  double pscale;        // 2 pi / L: momentum p_k = pscale * k'
+};
+
+// Per-item counters written by the propagation kernels.
+struct ItemStats {
+  long long h_applies;
+  long long iterations;
+  int solves;
+  int max_iters;
+  int failures;         // solves that hit maxit
+  int nonfinite;        // 1 if a norm became NaN/Inf (the item stops there)
+};
+
+struct SolveCfg {
+  double tol;
+  int m;        // restart length
+  int maxit;    // iterations per solve
+  int literal;  // 1: perform every explicit half-step
+};
+
+// Composition coefficients per recursion level l (raising order 2l+2 to 2l+4).  Both
+// schemes are symmetric with one distinct middle coefficient: triple jump
+// (g1, g2, g1), Suzuki (g1, g1, g3, g1, g1).  Digit d of a substep index selects
+// mid[l] when d == arity/2 and side[l] otherwise.
+struct GammaTab {
+  int arity;    // 3 (triple jump) or 5 (Suzuki)
+  int levels;   // order/2 - 1
+  int count;    // arity^levels substeps per step
+  double side[kMaxLevels];
+  double mid[kMaxLevels];
+};
+
+enum Method { kTrap = 0, kMidp = 1 };
+
+struct KArgs {
+  const ItemMeta* items;
+  const int* list;      // item indices of this launch's size class
+  int nlist;
+  const double* V;
+  const double* F;
+  double2* psi;         // state (in-place) / input
+  double2* aux;         // second state: H psi output, or lambda for the adjoint
+  double* gF;           // adjoint: dL/dF12 accumulation [n] per item (foff layout)
+  double* out;          // diagnostics output
+  double2* work;        // workspace base, (m + kWorkExtra) vectors of 2n per item
+  const double2* tw;    // exp(-2 pi i k / 4096)
+  double inv2m;         // 1 / (2 mass)
+  double mass;
+  SolveCfg sc;
+  int mode;             // 0 propagate, 1 reverse sweep
+  int method;
+  double dt;
+  long long nsteps;
+  GammaTab gt;
+  int hpsi_valid;       // trapezoid economy: HPSI slot already holds H psi
+  ItemStats* stats;
+};
+
+// LDS bytes needed by a launch at size N with restart length m.
+inline size_t lds_bytes(int N, int m) {
+  const int T = (N == 4096) ? 512 : (N / 4);  // threads per item (N / R0 of the plan)
+  const int W = T / 64;
+  const size_t c = 2 * (size_t)N + (size_t)W * (m + 1) + 2 * (m + 1) + 2 * (size_t)m +
+                   (size_t)m * (m + 1) / 2;
+  return c * 16 + (size_t)m * 8 + 16 * 8;
+}
+
+// Kernel launchers (gqd_kernels.hip).  Each launches one size class on `stream`.
+hipError_t launch_apply_h(int cls, const KArgs& a, hipStream_t stream);
+hipError_t launch_run(int cls, const KArgs& a, hipStream_t stream);  // propagate / adjoint
+hipError_t launch_diag(int cls, const KArgs& a, hipStream_t stream);
+hipError_t launch_inner(int cls, const KArgs& a, hipStream_t stream);
+hipError_t configure_kernels(int m_max);
+
+}  // namespace gqd

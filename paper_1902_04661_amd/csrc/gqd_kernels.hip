@@ -1,0 +1,855 @@
+// gfx950 kernels for the implicit geometric integrators of Choi & Vanicek,
+// J. Chem. Phys. 150, 204112 (2019).  One workgroup owns one 1D two-surface
+// wavepacket for a whole call: every H application, every Arnoldi iteration and
+// every composition substep of that item runs inside the workgroup, with vectors
+// on owned points in registers, the Fourier passes in LDS and the Krylov basis in
+// the item's slice of the workspace.
+#include "gqd_device.hpp"
+#include "gqd_internal.h"
+
+namespace gqd {
+
+static_assert(TW_N == kTwiddleN, "twiddle table size");
+
+template <int N>
+struct Eng {
+  using P = Plan<N>;
+  static constexpr int R0 = P::R0, R1 = P::R1, R2 = P::R2, R3 = P::R3;
+  static constexpr int T = N / R0;
+  static constexpr int W = T / 64;
+  static_assert(T % 64 == 0, "whole waves only");
+  static constexpr int RF = (R3 == 1) ? R2 : R3;  // radix of the fused k-space pass
+  static constexpr size_t VEC = 2 * (size_t)N;    // complex elements of one state vector
+
+  struct OV {
+    double2 v[2][R0];
+  };
+
+  struct Ctx {
+    double2* fft;   // [2N]
+    double2* part;  // [W][kmax]
+    double2* hcol;  // [kmax]
+    double2* g;     // [kmax]
+    double2* sn;    // [m]
+    double2* y;     // [m]
+    double2* R;     // [m(m+1)/2], column j at j(j+1)/2
+    double* cs;     // [m]
+    double* scal;   // [16]
+    int kmax;
+    const double* V;   // item's V, [2][N]
+    const double* F;   // item's F12, [N]
+    const double2* tw;
+    double pscale;
+    double inv2m;
+  };
+
+  // owned point r of this lane; lane_tid() keeps address arithmetic local to its use
+  static __device__ __forceinline__ int pt(int r) { return lane_tid() + r * T; }
+
+  static __device__ Ctx make_ctx(double2* smem, int m, const KArgs& a, const ItemMeta& im) {
+    Ctx c;
+    const int kmax = m + 1;
+    c.kmax = kmax;
+    c.fft = smem;
+    c.part = c.fft + 2 * N;
+    c.hcol = c.part + W * kmax;
+    c.g = c.hcol + kmax;
+    c.sn = c.g + kmax;
+    c.y = c.sn + m;
+    c.R = c.y + m;
+    c.cs = reinterpret_cast<double*>(c.R + (m * (m + 1)) / 2);
+    c.scal = c.cs + m;
+    c.V = a.V + im.voff;
+    c.F = a.F + im.foff;
+    c.tw = a.tw;
+    c.pscale = im.pscale;
+    c.inv2m = a.inv2m;
+    return c;
+  }
+
+  // ------------------------------------------------------------ owned-point vectors
+  static __device__ __forceinline__ void load(OV& x, const double2* __restrict__ g) {
+    g = opaque(g);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) x.v[s][r] = g[s * N + pt(r)];
+  }
+  static __device__ __forceinline__ void store(const OV& x, double2* __restrict__ g) {
+    g = opaque(g);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) g[s * N + pt(r)] = x.v[s][r];
+  }
+  static __device__ __forceinline__ double norm2(const OV& x) {
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) acc += cabs2(x.v[s][r]);
+    return acc;
+  }
+
+  // ------------------------------------------------------------------- reductions
+  // Workgroup sum of one real; every thread returns the same value (same order).
+  static __device__ double block_sum1(double v, const Ctx& c) {
+    v = wave_sum(v);
+    double* p = reinterpret_cast<double*>(c.part);
+    if ((threadIdx.x & 63) == 0) p[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) s += p[w];
+    __syncthreads();
+    return uniform_d(s);
+  }
+
+  // dst[i] = sum conj(V_i) w over the item, i < K (V_i = basis + i*VEC); dst in LDS.
+  static __device__ void block_dots(const double2* __restrict__ basis, const OV& w, int K,
+                                    const Ctx& c, double2* dst) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (int i = 0; i < K; ++i) {
+      const double2* Vi = opaque(basis + (size_t)i * VEC);
+      double ax = 0.0, ay = 0.0;
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          const double2 b = Vi[s * N + pt(r)];
+          const double2 z = w.v[s][r];
+          ax += b.x * z.x + b.y * z.y;
+          ay += b.x * z.y - b.y * z.x;
+        }
+      ax = wave_sum(ax);
+      ay = wave_sum(ay);
+      if (lane == 0) c.part[wv * c.kmax + i] = make_double2(ax, ay);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < K; i += T) {
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int w2 = 0; w2 < W; ++w2) s = cadd(s, c.part[w2 * c.kmax + i]);
+      dst[i] = s;
+    }
+    __syncthreads();
+  }
+
+  // w -= sum_i h[i] V_i, i < K (h in LDS)
+  static __device__ void block_axpy(const double2* __restrict__ basis, const double2* h, int K, OV& w) {
+#pragma unroll 1
+    for (int i = 0; i < K; ++i) {
+      const double2* Vi = opaque(basis + (size_t)i * VEC);
+      const double2 hi = h[i];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) w.v[s][r] = csub(w.v[s][r], cmul(hi, Vi[s * N + pt(r)]));
+    }
+  }
+
+  // --------------------------------------------------------------- Fourier passes
+  // Fused last forward pass (radix RF, Ns = N/RF), momentum multiply and first
+  // inverse pass (radix RF, Ns = 1): butterfly j's forward outputs are the k-space
+  // points j + r N/RF, exactly the inputs of the inverse butterfly j.
+  static __device__ __forceinline__ void fused_kspace(const Ctx& c, const double2* tw) {
+    constexpr int NB = 2 * N / RF;
+    static_assert(NB % T == 0, "fused pass butterflies");
+    constexpr int PER = NB / T;
+    constexpr int Ns = N / RF;
+    double2 x[PER][RF];
+    int tid = lane_tid();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int b = tid + q * T;
+      const int s = b / Ns, j = b % Ns;
+#pragma unroll
+      for (int r = 0; r < RF; ++r) x[q][r] = c.fft[s * N + j + r * Ns];
+    }
+    __syncthreads();
+    const double scale = opaque_d(c.pscale) / (double)N;
+    tid = lane_tid();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int b = tid + q * T;
+      const int s = b / Ns, j = b % Ns;
+      constexpr int step = TW_N / N;
+#pragma unroll
+      for (int r = 1; r < RF; ++r) x[q][r] = cmul(x[q][r], tw_lookup<-1>(tw, r * j * step));
+      DFT<RF, -1>::run(x[q]);
+#pragma unroll
+      for (int r = 0; r < RF; ++r) {
+        const int kk = j + r * Ns;                      // k-space index
+        const int kp = (kk < N / 2) ? kk : kk - N;      // signed wavenumber
+        x[q][r] = cscale(x[q][r], scale * (double)kp);  // p_k / N
+      }
+      DFT<RF, +1>::run(x[q]);
+#pragma unroll
+      for (int r = 0; r < RF; ++r) c.fft[s * N + j * RF + r] = x[q][r];
+    }
+    __syncthreads();
+  }
+
+  // u = p x on both surfaces (forward DFT, multiply by p_k, inverse DFT / N).
+  static __device__ void kinetic(const OV& x, OV& u, const Ctx& c) {
+    const double2* tw = opaque(c.tw);
+    // pass A: radix R0, Ns = 1, from owned registers (butterfly j = thread)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      double2 y[R0];
+#pragma unroll
+      for (int r = 0; r < R0; ++r) y[r] = x.v[s][r];
+      DFT<R0, -1>::run(y);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) c.fft[s * N + lane_tid() * R0 + r] = y[r];
+    }
+    __syncthreads();
+    if constexpr (R3 == 1) {
+      stockham_lds<N, T, R1, R0, -1>(c.fft, opaque(tw));
+      fused_kspace(c, opaque(tw));
+      stockham_lds<N, T, R1, R2, +1>(c.fft, opaque(tw));
+    } else {
+      stockham_lds<N, T, R1, R0, -1>(c.fft, opaque(tw));
+      stockham_lds<N, T, R2, R0 * R1, -1>(c.fft, opaque(tw));
+      fused_kspace(c, opaque(tw));
+      stockham_lds<N, T, R2, R3, +1>(c.fft, opaque(tw));
+      stockham_lds<N, T, R1, R3 * R2, +1>(c.fft, opaque(tw));
+    }
+    tw = opaque(tw);
+    // last inverse pass: radix R0, Ns = T, butterfly j = thread -> owned points
+    constexpr int step = TW_N / N;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      double2 y[R0];
+#pragma unroll
+      for (int r = 0; r < R0; ++r) y[r] = c.fft[s * N + pt(r)];
+#pragma unroll
+      for (int r = 1; r < R0; ++r) y[r] = cmul(y[r], tw_lookup<+1>(tw, r * lane_tid() * step));
+      DFT<R0, +1>::run(y);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) u.v[s][r] = y[r];
+    }
+    __syncthreads();  // the LDS buffer is free again
+  }
+
+  // y = [p - i F] x for x at xg (F12 couples surface 2 into surface 1, F21 = -F12).
+  // The input is re-read at owned points after the transform.
+  static __device__ void apply_A(const double2* xg, OV& y, const Ctx& c) {
+    {
+      OV t;
+      load(t, xg);
+      kinetic(t, y, c);
+    }
+    const double* F = opaque(c.F);
+    xg = opaque(xg);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const double f = F[pt(r)];
+      const double2 x0 = xg[pt(r)], x1 = xg[N + pt(r)];
+      // -i f x2 added to surface 1, +i f x1 added to surface 2
+      y.v[0][r] = cadd(y.v[0][r], cmul_is(x1, -f));
+      y.v[1][r] = cadd(y.v[1][r], cmul_is(x0, f));
+    }
+  }
+
+  // y <- y / (2m) + V x: completes H x = A (A x) / (2m) + V x after the second A pass.
+  static __device__ __forceinline__ void finish_H(OV& y, const double2* xg, const Ctx& c) {
+    const double* V = opaque(c.V);
+    xg = opaque(xg);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int r = 0; r < R0; ++r)
+        y.v[s][r] = cadd(cscale(y.v[s][r], c.inv2m), cscale(xg[s * N + pt(r)], V[s * N + pt(r)]));
+  }
+
+  // --------------------------------------------------------------------- GMRES
+  // Thread 0 applies the stored rotations to the new Hessenberg column, forms the
+  // new rotation from (column[j], hn), stores column j of R and updates g.
+  static __device__ void givens_update(int j, double hn, const Ctx& c) {
+    if (threadIdx.x == 0) {
+      double2* h = c.hcol;
+      for (int i = 0; i < j; ++i) {
+        const double ci = c.cs[i];
+        const double2 si = c.sn[i];
+        const double2 hi = h[i], hi1 = h[i + 1];
+        const double2 t = cadd(cscale(hi, ci), cmul(si, hi1));
+        h[i + 1] = cadd(cmul(cneg(make_double2(si.x, -si.y)), hi), cscale(hi1, ci));
+        h[i] = t;
+      }
+      const double2 a = h[j];
+      double cj;
+      double2 sj, rj;
+      if (hn == 0.0) {
+        cj = 1.0;
+        sj = make_double2(0.0, 0.0);
+        rj = a;
+      } else if (a.x == 0.0 && a.y == 0.0) {
+        cj = 0.0;
+        sj = make_double2(1.0, 0.0);
+        rj = make_double2(hn, 0.0);
+      } else {
+        const double absa = hypot(a.x, a.y);
+        const double rho = sqrt(absa * absa + hn * hn);
+        const double2 ph = make_double2(a.x / absa, a.y / absa);
+        cj = absa / rho;
+        sj = cscale(ph, hn / rho);
+        rj = cscale(ph, rho);
+      }
+      c.cs[j] = cj;
+      c.sn[j] = sj;
+      double2* Rj = c.R + (j * (j + 1)) / 2;
+      for (int i = 0; i < j; ++i) Rj[i] = h[i];
+      Rj[j] = rj;
+      const double2 gj = c.g[j];
+      c.g[j + 1] = cmul(cneg(make_double2(sj.x, -sj.y)), gj);
+      c.g[j] = cscale(gj, cj);
+      c.scal[0] = hypot(c.g[j + 1].x, c.g[j + 1].y);
+    }
+    __syncthreads();
+  }
+
+  // Thread 0: y = R^-1 g (upper triangular, k columns).
+  static __device__ void back_solve(int k, const Ctx& c) {
+    if (threadIdx.x == 0) {
+      for (int i = k - 1; i >= 0; --i) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int l = i + 1; l < k; ++l) s = cadd(s, cmul(c.R[(l * (l + 1)) / 2 + i], c.y[l]));
+        const double2 num = csub(c.g[i], s);
+        const double2 d = c.R[(i * (i + 1)) / 2 + i];
+        const double dd = d.x * d.x + d.y * d.y;
+        c.y[i] = make_double2((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd);
+      }
+    }
+    __syncthreads();
+  }
+};
+
+// composition fraction tau_c: product of one gamma per level, innermost level first
+// (the flattened list of Sec. II.D with gamma_1 applied first)
+__device__ __forceinline__ double substep_tau(int c, const GammaTab& gt) {
+  double t = 1.0;
+  int cc = c;
+  const int mid = gt.arity / 2;
+#pragma unroll
+  for (int l = 0; l < kMaxLevels; ++l) {
+    if (l < gt.levels) {
+      const int d = cc % gt.arity;
+      cc /= gt.arity;
+      t = (d == mid ? gt.mid[l] : gt.side[l]) * t;
+    }
+  }
+  return t;
+}
+
+// ------------------------------------------------------------------------ kernels
+
+// Program counter values of the propagation machine (see k_run).
+enum Pc {
+  kSubstep,       // start the next substep (or finish)
+  kSolveGuess,    // have H b: form x0 = (1 - i al H) b, ask for H x0
+  kSolveResid,    // have H x: true residual, restart or finish the solve
+  kSolveArnoldi,  // have H v_j: Arnoldi step j
+  kMidpAfter,     // midpoint: x solved
+  kMidpExplicit,  // midpoint, literal: have H x
+  kTrapHpsi,      // trapezoid: have H psi
+  kTrapAfter,     // trapezoid: psi' solved
+  kAdjAfterPhi,   // adjoint: phi solved
+  kAdjAfterMu,    // adjoint: mu solved
+  kAdjAphi,       // adjoint: have A phi
+  kAdjAmu         // adjoint: have A mu
+};
+
+// Whole-call propagation (mode 0) or reverse sweep (mode 1) of one item per workgroup.
+//
+// The kernel is a small machine around a single operator application so that the
+// Fourier-transform code exists once: each loop turn applies A = p - iF to a global
+// vector (H takes two turns, the inner A x parked in the CHI slot), then the current
+// program counter consumes the result and requests the next application.
+//
+// Propagation, per substep of length h = tau_c dt, alpha = h/2 (Sec. II.C-D):
+//   midpoint (Eq. 19):  x = (1 + i alpha H)^-1 psi;  psi' = (1 - i alpha H) x, or 2x - psi
+//   trapezoid (Eq. 18): b = (1 - i alpha H) psi;     psi' = (1 + i alpha H)^-1 b
+// Each inverse is restarted GMRES(m) from x0 = (1 - i alpha H) b with classical
+// Gram-Schmidt applied twice and Givens rotations; it stops when the residual
+// estimate is <= tol ||b||.
+//
+// Reverse sweep, substeps in reverse order: phi = (1 - i alpha H)^-1 psi,
+// mu = (1 - i alpha H)^-1 lambda, psi <- 2 phi - psi, lambda <- 2 mu - lambda,
+// gF += -(2 alpha / m) Re[conj(mu1)(A phi)2 - conj(mu2)(A phi)1 + conj(A mu)1 phi2 - conj(A mu)2 phi1].
+template <int N>
+__global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
+  using E = Eng<N>;
+  using OV = typename E::OV;
+  constexpr int R0 = E::R0;
+  constexpr int T = E::T;
+  if ((int)blockIdx.x >= a.nlist) return;
+  extern __shared__ double2 smem[];
+  const int item = a.list[blockIdx.x];
+  const ItemMeta im = a.items[item];
+  const int m = a.sc.m;
+  double2* work = a.work + im.off * (long long)(m + kWorkExtra);
+  const auto c = E::make_ctx(smem, m, a, im);
+  double2* psi = a.psi + im.off;
+  double2* lam = a.aux + im.off;
+  double2* basis = work;
+  double2* S0 = work + (size_t)(m + 1) * E::VEC;  // X (solve output)  | PHI
+  double2* S1 = S0 + E::VEC;                       // B (rhs, H x)      | MU
+  double2* S2 = S1 + E::VEC;                       // HPSI              | A phi
+  double2* S3 = S2 + E::VEC;                       //                   | A mu
+  double2* CHI = S3 + E::VEC;                      // inner A x of an H application
+  const bool adj = a.mode == 1;
+  const bool midp = a.method == kMidp;
+  const bool literal = a.sc.literal != 0;
+
+  long long napply = 0, iters_total = 0;
+  int solves = 0, max_iters = 0, failures = 0;
+  bool bad = false;
+  bool have_hpsi = a.hpsi_valid != 0;
+
+  long long n = 0;
+  int cc = adj ? a.gt.count - 1 : 0;
+  double alpha = 0.0;
+
+  // operator request
+  bool pending = false, opH = false;
+  int half = 0;
+  const double2* opsrc = nullptr;
+  // solve state
+  const double2* bg = nullptr;
+  double2* xg = nullptr;
+  double al = 0.0, tolb = 0.0;
+  int j = 0, iters = 0, after = kSubstep;
+
+  int pc = kSubstep;
+  OV y;
+
+  auto request = [&](const double2* src, bool h) {
+    pending = true;
+    opsrc = src;
+    opH = h;
+    half = 0;
+  };
+  // start a solve of (1 + i al H) x = b: ||b||, then ask for H b
+  auto solve_begin = [&](const double2* b, double2* x, double alv, int ret) {
+    bg = b;
+    xg = x;
+    al = alv;
+    after = ret;
+    iters = 0;
+    OV t;
+    E::load(t, b);
+    const double bnorm = sqrt(E::block_sum1(E::norm2(t), c));
+    if (!isfinite(bnorm)) bad = true;
+    tolb = a.sc.tol * bnorm;
+    request(b, true);
+    pc = kSolveGuess;
+  };
+  auto solve_end = [&](bool conv) {
+    ++solves;
+    iters_total += iters;
+    if (iters > max_iters) max_iters = iters;
+    if (!conv) ++failures;
+    pc = after;
+  };
+  auto advance = [&]() {
+    if (adj) {
+      if (--cc < 0) {
+        cc = a.gt.count - 1;
+        ++n;
+      }
+    } else if (++cc == a.gt.count) {
+      cc = 0;
+      ++n;
+    }
+    pc = kSubstep;
+  };
+
+  for (;;) {
+    if (bad) break;
+    if (pending) {
+      E::apply_A(half == 0 ? opsrc : CHI, y, c);
+      if (opH && half == 0) {
+        E::store(y, CHI);
+        half = 1;
+        continue;
+      }
+      if (opH) {
+        E::finish_H(y, opsrc, c);
+        ++napply;
+      }
+      pending = false;
+    }
+    switch (pc) {
+      case kSubstep: {
+        if (n >= a.nsteps) goto done;
+        alpha = 0.5 * (substep_tau(cc, a.gt) * a.dt);
+        if (adj) {
+          solve_begin(psi, S0, -alpha, kAdjAfterPhi);
+        } else if (midp) {
+          solve_begin(psi, S0, alpha, kMidpAfter);
+        } else if (literal || !have_hpsi) {
+          request(psi, true);
+          pc = kTrapHpsi;
+        } else {
+          pc = kTrapHpsi;  // H psi already in S2
+        }
+        break;
+      }
+      case kTrapHpsi: {
+        OV p, q;
+        if (literal || !have_hpsi) {
+          E::store(y, S2);
+          q = y;
+        } else {
+          E::load(q, S2);
+        }
+        E::load(p, psi);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) p.v[s][r] = csub(p.v[s][r], cmul_is(q.v[s][r], alpha));
+        E::store(p, S1);  // b = (1 - i alpha H) psi
+        solve_begin(S1, psi, alpha, kTrapAfter);
+        break;
+      }
+      case kTrapAfter: {
+        if (!literal) {
+          // H psi' = (b - psi') / (i alpha), reused by the next substep's explicit half
+          OV p, q;
+          E::load(p, S1);
+          E::load(q, psi);
+#pragma unroll
+          for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+              const double2 d = csub(p.v[s][r], q.v[s][r]);
+              q.v[s][r] = make_double2(d.y / alpha, -d.x / alpha);
+            }
+          E::store(q, S2);
+          have_hpsi = true;
+        }
+        advance();
+        break;
+      }
+      case kMidpAfter: {
+        if (literal) {
+          request(S0, true);
+          pc = kMidpExplicit;
+          break;
+        }
+        OV p, q;  // psi' = 2x - psi
+        E::load(q, S0);
+        E::load(p, psi);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) p.v[s][r] = csub(cscale(q.v[s][r], 2.0), p.v[s][r]);
+        E::store(p, psi);
+        advance();
+        break;
+      }
+      case kMidpExplicit: {
+        OV q;  // psi' = x - i alpha H x
+        E::load(q, S0);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) q.v[s][r] = csub(q.v[s][r], cmul_is(y.v[s][r], alpha));
+        E::store(q, psi);
+        advance();
+        break;
+      }
+      case kSolveGuess: {
+        OV t;
+        E::load(t, bg);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) y.v[s][r] = csub(t.v[s][r], cmul_is(y.v[s][r], al));
+        E::store(y, xg);  // x0 = (1 - i al H) b
+        request(xg, true);
+        pc = kSolveResid;
+        break;
+      }
+      case kSolveResid: {
+        OV t;
+        E::load(t, xg);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) y.v[s][r] = cadd(t.v[s][r], cmul_is(y.v[s][r], al));
+        E::load(t, bg);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) y.v[s][r] = csub(t.v[s][r], y.v[s][r]);  // r = b - X x
+        const double beta = sqrt(E::block_sum1(E::norm2(y), c));
+        if (!isfinite(beta)) {
+          bad = true;
+          break;
+        }
+        if (beta <= tolb) {
+          solve_end(true);
+          break;
+        }
+        if (iters >= a.sc.maxit) {
+          solve_end(false);
+          break;
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) y.v[s][r] = make_double2(y.v[s][r].x / beta, y.v[s][r].y / beta);
+        E::store(y, basis);
+        if (threadIdx.x == 0) c.g[0] = make_double2(beta, 0.0);
+        // (the next block reduction's barrier orders this write before any read)
+        j = 0;
+        request(basis, true);
+        pc = kSolveArnoldi;
+        break;
+      }
+      case kSolveArnoldi: {
+        const double2* Vj = basis + (size_t)j * E::VEC;
+        ++iters;
+        {
+          OV t;
+          E::load(t, Vj);
+#pragma unroll
+          for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) y.v[s][r] = cadd(t.v[s][r], cmul_is(y.v[s][r], al));
+        }
+        E::block_dots(basis, y, j + 1, c, c.hcol);
+        E::block_axpy(basis, c.hcol, j + 1, y);
+        E::block_dots(basis, y, j + 1, c, c.y);
+        E::block_axpy(basis, c.y, j + 1, y);
+        for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);
+        const double hn = sqrt(E::block_sum1(E::norm2(y), c));  // its barriers order the hcol update
+        E::givens_update(j, hn, c);
+        const double gabs = uniform_d(c.scal[0]);
+        if (!isfinite(hn) || !isfinite(gabs)) {
+          bad = true;
+          break;
+        }
+        const bool cv = gabs <= tolb;
+        if (!cv && hn != 0.0 && iters < a.sc.maxit && j + 1 < m) {
+#pragma unroll
+          for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) y.v[s][r] = make_double2(y.v[s][r].x / hn, y.v[s][r].y / hn);
+          ++j;
+          E::store(y, basis + (size_t)j * E::VEC);
+          request(basis + (size_t)j * E::VEC, true);
+          break;
+        }
+        // cycle ends: x += V y over the k = j + 1 basis vectors
+        const int k = j + 1;
+        E::back_solve(k, c);
+        {
+          OV x;
+          E::load(x, xg);
+#pragma unroll 1
+          for (int i = 0; i < k; ++i) {
+            const double2* Vi = basis + (size_t)i * E::VEC;
+            const double2 yi = c.y[i];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+              for (int r = 0; r < R0; ++r) x.v[s][r] = cadd(x.v[s][r], cmul(yi, Vi[s * N + E::pt(r)]));
+          }
+          E::store(x, xg);
+        }
+        __syncthreads();  // y is read by all before it can be rewritten
+        if (cv) {
+          solve_end(true);
+        } else {  // restart, or maxit / breakdown: the true residual decides
+          request(xg, true);
+          pc = kSolveResid;
+        }
+        break;
+      }
+      case kAdjAfterPhi:
+        solve_begin(lam, S1, -alpha, kAdjAfterMu);
+        break;
+      case kAdjAfterMu:
+        request(S0, false);
+        pc = kAdjAphi;
+        break;
+      case kAdjAphi:
+        E::store(y, S2);
+        request(S1, false);
+        pc = kAdjAmu;
+        break;
+      case kAdjAmu: {
+        E::store(y, S3);
+        double* gF = a.gF + im.foff;
+        const double coef = -(2.0 * alpha / a.mass);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          const int i0 = E::pt(r), i1 = N + E::pt(r);
+          const double t = cconjmul(S1[i0], S2[i1]).x - cconjmul(S1[i1], S2[i0]).x +
+                           cconjmul(S3[i0], S0[i1]).x - cconjmul(S3[i1], S0[i0]).x;
+          gF[E::pt(r)] += coef * t;
+        }
+        OV p, t;
+        E::load(p, psi);
+        E::load(t, S0);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) p.v[s][r] = csub(cscale(t.v[s][r], 2.0), p.v[s][r]);
+        E::store(p, psi);
+        E::load(p, lam);
+        E::load(t, S1);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) p.v[s][r] = csub(cscale(t.v[s][r], 2.0), p.v[s][r]);
+        E::store(p, lam);
+        advance();
+        break;
+      }
+      default:
+        bad = true;
+        break;
+    }
+  }
+done:
+  if (threadIdx.x == 0 && a.stats) {
+    ItemStats* st = a.stats + item;
+    st->h_applies = napply;
+    st->iterations = iters_total;
+    st->solves = solves;
+    st->max_iters = max_iters;
+    st->failures = failures;
+    st->nonfinite = bad ? 1 : 0;
+  }
+}
+
+// aux = H psi; aux doubles as the parking slot of the inner A psi
+template <int N>
+__global__ void __launch_bounds__(Eng<N>::T) k_apply_h(KArgs a) {
+  using E = Eng<N>;
+  if ((int)blockIdx.x >= a.nlist) return;
+  extern __shared__ double2 smem[];
+  const ItemMeta im = a.items[a.list[blockIdx.x]];
+  const auto c = E::make_ctx(smem, 0, a, im);
+  typename E::OV y;
+  E::apply_A(a.psi + im.off, y, c);
+  E::store(y, a.aux + im.off);
+  E::apply_A(a.aux + im.off, y, c);
+  E::finish_H(y, a.psi + im.off, c);
+  E::store(y, a.aux + im.off);
+}
+
+// out[item] = (norm, energy, P1, P2); energy = ||A psi||^2 / (2m) + <psi|V psi>
+template <int N>
+__global__ void __launch_bounds__(Eng<N>::T) k_diag(KArgs a) {
+  using E = Eng<N>;
+  if ((int)blockIdx.x >= a.nlist) return;
+  extern __shared__ double2 smem[];
+  const int item = a.list[blockIdx.x];
+  const ItemMeta im = a.items[item];
+  const auto c = E::make_ctx(smem, 0, a, im);
+  const double2* x = a.psi + im.off;
+  double p0 = 0.0, p1 = 0.0, pv = 0.0;
+#pragma unroll
+  for (int r = 0; r < E::R0; ++r) {
+    const double a0 = cabs2(x[E::pt(r)]), a1 = cabs2(x[N + E::pt(r)]);
+    p0 += a0;
+    p1 += a1;
+    pv += c.V[E::pt(r)] * a0 + c.V[N + E::pt(r)] * a1;
+  }
+  typename E::OV ax;
+  E::apply_A(x, ax, c);
+  const double ka = E::norm2(ax);
+  const double P0 = E::block_sum1(p0, c) * im.dq;
+  const double P1 = E::block_sum1(p1, c) * im.dq;
+  const double PV = E::block_sum1(pv, c) * im.dq;
+  const double KA = E::block_sum1(ka, c) * im.dq;
+  if (threadIdx.x == 0) {
+    double* o = a.out + 4 * (size_t)item;
+    o[0] = sqrt(P0 + P1);
+    o[1] = KA * a.inv2m + PV;
+    o[2] = P0;
+    o[3] = P1;
+  }
+}
+
+// out[2 item], out[2 item + 1] = Re, Im <psi|aux> = dq * sum conj(psi) aux
+template <int N>
+__global__ void __launch_bounds__(Eng<N>::T) k_inner(KArgs a) {
+  using E = Eng<N>;
+  if ((int)blockIdx.x >= a.nlist) return;
+  extern __shared__ double2 smem[];
+  const int item = a.list[blockIdx.x];
+  const ItemMeta im = a.items[item];
+  const auto c = E::make_ctx(smem, 0, a, im);
+  const double2* x = a.psi + im.off;
+  const double2* y = a.aux + im.off;
+  double re = 0.0, imv = 0.0;
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int r = 0; r < E::R0; ++r) {
+      const double2 z = cconjmul(x[s * N + E::pt(r)], y[s * N + E::pt(r)]);
+      re += z.x;
+      imv += z.y;
+    }
+  re = E::block_sum1(re, c) * im.dq;
+  imv = E::block_sum1(imv, c) * im.dq;
+  if (threadIdx.x == 0) {
+    a.out[2 * (size_t)item] = re;
+    a.out[2 * (size_t)item + 1] = imv;
+  }
+}
+
+// --------------------------------------------------------------------- launchers
+
+#define GQD_DISPATCH(cls, EXPR)                      \
+  switch (cls) {                                     \
+    case 0: { constexpr int N = 256;  EXPR; } break; \
+    case 1: { constexpr int N = 512;  EXPR; } break; \
+    case 2: { constexpr int N = 1024; EXPR; } break; \
+    case 3: { constexpr int N = 2048; EXPR; } break; \
+    case 4: { constexpr int N = 4096; EXPR; } break; \
+    default: return hipErrorInvalidValue;            \
+  }
+
+template <int N>
+static hipError_t set_lds_limit(size_t bytes) {
+  hipError_t e;
+  if ((e = hipFuncSetAttribute((const void*)k_apply_h<N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_run<N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_diag<N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_inner<N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t configure_kernels(int m_max) {
+  for (int cls = 0; cls < kNumClasses; ++cls) {
+    hipError_t e = hipSuccess;
+    GQD_DISPATCH(cls, {
+      size_t bytes = lds_bytes(N, m_max);
+      if (bytes > 160 * 1024) bytes = 160 * 1024;
+      e = set_lds_limit<N>(bytes);
+    });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+#define GQD_LAUNCH(KERNEL, M_LDS)                                                                  \
+  GQD_DISPATCH(cls, {                                                                             \
+    if (a.nlist <= 0) return hipSuccess;                                                          \
+    hipLaunchKernelGGL(KERNEL<N>, dim3(a.nlist), dim3(Eng<N>::T), lds_bytes(N, M_LDS), stream, a); \
+  });                                                                                             \
+  return hipGetLastError();
+
+hipError_t launch_apply_h(int cls, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_apply_h, 0) }
+hipError_t launch_run(int cls, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_run, a.sc.m) }
+hipError_t launch_diag(int cls, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_diag, 0) }
+hipError_t launch_inner(int cls, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_inner, 0) }
+
+}  // namespace gqd

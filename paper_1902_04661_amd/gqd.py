@@ -1,0 +1,295 @@
+"""Thin Python binding of the gqd C ABI (include/gqd.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP library
+libgqd.so.  PyTorch supplies device memory and the stream.  There is no CPU
+fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgqd.so")
+
+TRAP, MIDP = 0, 1
+TRIPLE_JUMP, SUZUKI = 0, 1
+_METHODS = {"trap": TRAP, "midp": MIDP, TRAP: TRAP, MIDP: MIDP}
+_SCHEMES = {"triple_jump": TRIPLE_JUMP, "suzuki": SUZUKI, TRIPLE_JUMP: TRIPLE_JUMP, SUZUKI: SUZUKI}
+SIZES = (256, 512, 1024, 2048, 4096)
+
+STATUS = {0: "OK", -1: "INVALID", -2: "HIP", -3: "NOMEM", -4: "NOT_CONVERGED",
+          -5: "UNSUPPORTED", -6: "NONFINITE", -7: "STATE"}
+
+
+class GqdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gqd {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class NotConverged(GqdError):
+    pass
+
+
+class _GridDesc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int), ("surfaces", ctypes.c_int), ("batch", ctypes.c_int),
+                ("n", ctypes.POINTER(ctypes.c_int)), ("qmin", ctypes.POINTER(ctypes.c_double)),
+                ("qmax", ctypes.POINTER(ctypes.c_double)), ("mass", ctypes.POINTER(ctypes.c_double))]
+
+
+class _SolverOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
+                ("literal", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("h_applies", ctypes.c_longlong), ("iterations", ctypes.c_longlong),
+                ("solves", ctypes.c_longlong), ("max_iters", ctypes.c_int),
+                ("failures", ctypes.c_int), ("failed_item", ctypes.c_int),
+                ("nonfinite", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgqd.so (built in-tree by build.py); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    sig = {
+        "gqd_create": ([ctypes.POINTER(vp), ctypes.POINTER(_GridDesc)], i),
+        "gqd_destroy": ([vp], None),
+        "gqd_state_size": ([vp, ctypes.POINTER(ll)], i),
+        "gqd_state_offset": ([vp, i, ctypes.POINTER(ll)], i),
+        "gqd_workspace_size": ([vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(ctypes.c_size_t)], i),
+        "gqd_set_workspace": ([vp, vp, ctypes.c_size_t], i),
+        "gqd_set_surfaces": ([vp, vp, vp], i),
+        "gqd_apply_H": ([vp, vp, vp, vp], i),
+        "gqd_implicit_step": ([vp, i, d, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
+        "gqd_propagate": ([vp, i, i, i, d, ll, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
+        "gqd_adjoint": ([vp, i, i, d, ll, vp, vp, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
+        "gqd_diag": ([vp, vp, vp, vp], i),
+        "gqd_inner": ([vp, vp, vp, vp, vp], i),
+        "gqd_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (argtypes, restype) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = argtypes
+        fn.restype = restype
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> List[str]:
+    return ["gqd_create", "gqd_destroy", "gqd_state_size", "gqd_state_offset",
+            "gqd_workspace_size", "gqd_set_workspace", "gqd_set_surfaces", "gqd_apply_H",
+            "gqd_implicit_step", "gqd_propagate", "gqd_adjoint", "gqd_diag", "gqd_inner",
+            "gqd_last_error"]
+
+
+def _check(code: int):
+    if code != 0:
+        msg = _lib.gqd_last_error().decode()
+        if code == -4:
+            raise NotConverged(code, msg)
+        raise GqdError(code, msg)
+
+
+@dataclass
+class SolverOpts:
+    tol: float = 1e-13
+    restart: int = 32
+    maxit: int = 1000
+    literal: bool = False
+
+    def c(self) -> _SolverOpts:
+        return _SolverOpts(float(self.tol), int(self.restart), int(self.maxit), int(bool(self.literal)))
+
+
+@dataclass
+class Stats:
+    h_applies: int
+    iterations: int
+    solves: int
+    max_iters: int
+    failures: int
+    failed_item: int
+    nonfinite: int
+
+
+def _stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Propagator:
+    """A batch of 1D two-surface wavepackets on one GPU.
+
+    n, qmin, qmax: per item; mass: nuclear mass.  V (batch of [2][n]) and F ([n])
+    are given as numpy arrays or device tensors and kept on the device.
+    """
+
+    def __init__(self, n: Sequence[int], qmin: Sequence[float], qmax: Sequence[float],
+                 mass: float, V=None, F=None, device: str = "cuda"):
+        lib = load_library()
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.n = np.asarray(n, dtype=np.int32).ravel()
+        self.batch = int(self.n.size)
+        self.qmin = np.broadcast_to(np.asarray(qmin, dtype=np.float64), (self.batch,)).copy()
+        self.qmax = np.broadcast_to(np.asarray(qmax, dtype=np.float64), (self.batch,)).copy()
+        self.mass = float(mass)
+        self._mass = np.array([self.mass], dtype=np.float64)
+        desc = _GridDesc(1, 2, self.batch,
+                         self.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                         self.qmin.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         self.qmax.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         self._mass.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)))
+        self._h = h
+        total = ctypes.c_longlong()
+        _check(lib.gqd_state_size(h, ctypes.byref(total)))
+        self.state_size = int(total.value)
+        self.offsets = np.concatenate([[0], np.cumsum(2 * self.n.astype(np.int64))])
+        self._work = None
+        self._work_m = -1
+        self.V = None
+        self.F = None
+        if V is not None and F is not None:
+            self.set_surfaces(V, F)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) is not None and _lib is not None:
+                _lib.gqd_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- data layout
+    def pack(self, arrays) -> torch.Tensor:
+        """Concatenate per-item complex arrays of shape (2, n_b) into one device state."""
+        flat = np.concatenate([np.asarray(a, dtype=np.complex128).reshape(-1) for a in arrays])
+        assert flat.size == self.state_size
+        return torch.from_numpy(flat).to(self.device)
+
+    def unpack(self, psi: torch.Tensor) -> List[np.ndarray]:
+        host = psi.detach().cpu().numpy()
+        return [host[self.offsets[b]:self.offsets[b + 1]].reshape(2, -1) for b in range(self.batch)]
+
+    def set_surfaces(self, V, F):
+        """V: per-item (2, n_b) float64 (or a flat device tensor); F: per-item (n_b,) or (1, n_b)."""
+        if isinstance(V, torch.Tensor):
+            Vt = V.to(self.device, torch.float64).contiguous().reshape(-1)
+        else:
+            Vt = torch.from_numpy(np.concatenate([np.asarray(v, np.float64).reshape(-1) for v in V])).to(self.device)
+        if isinstance(F, torch.Tensor):
+            Ft = F.to(self.device, torch.float64).contiguous().reshape(-1)
+        else:
+            Ft = torch.from_numpy(np.concatenate([np.asarray(f, np.float64).reshape(-1) for f in F])).to(self.device)
+        if Vt.numel() != self.state_size or Ft.numel() != self.state_size // 2:
+            raise ValueError("V or F has the wrong size for this grid")
+        self.V, self.F = Vt, Ft
+        _check(_lib.gqd_set_surfaces(self._h, ctypes.c_void_p(Vt.data_ptr()), ctypes.c_void_p(Ft.data_ptr())))
+
+    def _ensure_workspace(self, opts: SolverOpts):
+        if self._work is not None and self._work_m >= opts.restart:
+            return
+        nbytes = ctypes.c_size_t()
+        co = opts.c()
+        _check(_lib.gqd_workspace_size(self._h, ctypes.byref(co), ctypes.byref(nbytes)))
+        self._work = torch.empty(int(nbytes.value) // 16 + 1, dtype=torch.complex128, device=self.device)
+        self._work_m = opts.restart
+        _check(_lib.gqd_set_workspace(self._h, ctypes.c_void_p(self._work.data_ptr()), self._work.numel() * 16))
+
+    def _state(self, psi: torch.Tensor) -> ctypes.c_void_p:
+        if psi.dtype != torch.complex128 or not psi.is_contiguous() or psi.numel() != self.state_size \
+                or psi.device != self.device:
+            raise ValueError("state must be a contiguous complex128 device tensor of state_size elements")
+        return ctypes.c_void_p(psi.data_ptr())
+
+    # ------------------------------------------------------------------- calls
+    def apply_H(self, psi: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        out = torch.empty_like(psi) if out is None else out
+        _check(_lib.gqd_apply_H(self._h, self._state(psi), self._state(out), _stream_ptr(stream)))
+        return out
+
+    def propagate(self, psi: torch.Tensor, method="midp", scheme="suzuki", order: int = 2,
+                  dt: float = 1.0, nsteps: int = 1, opts: Optional[SolverOpts] = None,
+                  stats: bool = True, stream=None) -> Optional[Stats]:
+        """In place: nsteps composed steps.  With stats=True the call waits and returns
+        solver counters (and raises NotConverged if any solve hit maxit)."""
+        opts = opts or SolverOpts()
+        self._ensure_workspace(opts)
+        co = opts.c()
+        st = _Stats() if stats else None
+        _check(_lib.gqd_propagate(self._h, _METHODS[method], _SCHEMES[scheme], int(order), float(dt),
+                                  int(nsteps), self._state(psi), ctypes.byref(co),
+                                  ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
+        return Stats(st.h_applies, st.iterations, st.solves, st.max_iters, st.failures,
+                     st.failed_item, st.nonfinite) if st is not None else None
+
+    def implicit_step(self, psi: torch.Tensor, method="midp", dt: float = 1.0,
+                      opts: Optional[SolverOpts] = None, stats: bool = True, stream=None):
+        opts = opts or SolverOpts()
+        self._ensure_workspace(opts)
+        co = opts.c()
+        st = _Stats() if stats else None
+        _check(_lib.gqd_implicit_step(self._h, _METHODS[method], float(dt), self._state(psi), ctypes.byref(co),
+                                      ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
+        return Stats(st.h_applies, st.iterations, st.solves, st.max_iters, st.failures,
+                     st.failed_item, st.nonfinite) if st is not None else None
+
+    def adjoint(self, psi: torch.Tensor, lam: torch.Tensor, gF: torch.Tensor, scheme="suzuki",
+                order: int = 2, dt: float = 1.0, nsteps: int = 1, opts: Optional[SolverOpts] = None,
+                stats: bool = True, stream=None):
+        """In place reverse sweep: psi(T) -> psi(0), lam = dL/dpsi*(T) -> (0); gF += dL/dF12."""
+        opts = opts or SolverOpts()
+        self._ensure_workspace(opts)
+        if gF.dtype != torch.float64 or gF.numel() != self.state_size // 2 or not gF.is_contiguous():
+            raise ValueError("gF must be a contiguous float64 tensor with one entry per grid point")
+        co = opts.c()
+        st = _Stats() if stats else None
+        _check(_lib.gqd_adjoint(self._h, _SCHEMES[scheme], int(order), float(dt), int(nsteps),
+                                self._state(psi), self._state(lam), ctypes.c_void_p(gF.data_ptr()),
+                                ctypes.byref(co), ctypes.byref(st) if st is not None else None,
+                                _stream_ptr(stream)))
+        return Stats(st.h_applies, st.iterations, st.solves, st.max_iters, st.failures,
+                     st.failed_item, st.nonfinite) if st is not None else None
+
+    def diag(self, psi: torch.Tensor, stream=None) -> torch.Tensor:
+        """(batch, 4): norm, energy, population of surface 1, of surface 2."""
+        out = torch.empty(self.batch * 4, dtype=torch.float64, device=self.device)
+        _check(_lib.gqd_diag(self._h, self._state(psi), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out.reshape(self.batch, 4)
+
+    def inner(self, psi: torch.Tensor, phi: torch.Tensor, stream=None) -> torch.Tensor:
+        out = torch.empty(self.batch * 2, dtype=torch.float64, device=self.device)
+        _check(_lib.gqd_inner(self._h, self._state(psi), self._state(phi), ctypes.c_void_p(out.data_ptr()),
+                              _stream_ptr(stream)))
+        o = out.reshape(self.batch, 2)
+        return torch.complex(o[:, 0], o[:, 1])
+
+
+def from_items(items, device: str = "cuda") -> Propagator:
+    """Propagator for a list of input items (objects with n, qmin, qmax, mass, V, F)."""
+    masses = {float(it.mass) for it in items}
+    if len(masses) != 1:
+        raise ValueError("all items must share one mass")
+    return Propagator([it.n for it in items], [it.qmin for it in items], [it.qmax for it in items],
+                      masses.pop(), [it.V for it in items], [it.F for it in items], device=device)
