@@ -1,0 +1,198 @@
+"""Benchmark: grid-point.steps/s of 8th-order composed implicit midpoint at the step
+that reaches convergence error 1e-10, on one MI355X.
+
+Workload.  The two-surface NaI-like adiabatic model on N = 2048 points of [3, 16) bohr
+(Morse + repulsive surfaces, Gaussian coupling), Suzuki-fractal composition of the
+implicit midpoint method to order 8 (125 substeps per step), step dt = 10 a.u. (the
+largest dt_k = 40 * 2^-k whose error at T = 4000 a.u. against the dt/8 order-8
+reference is <= 1e-10; see paper_1902_04661_amd.convergence), GMRES tolerance 1e-14.
+A batch of B wavepackets with seeded centres, momenta and coupling amplitudes
+(U[4.5, 6], U[-5, 5], U[0.1, 0.8]; numpy default_rng(0)) fills the GPU; one "step"
+advances every packet by dt in one kernel launch.  The same model with one packet is
+timed too (single_packet).
+
+Roofline: the propagation kernel against the HBM peak (8 TB/s) with algorithmic bytes
+32 (I^2 + 4I + 8) per grid point per substep for a solve of I Arnoldi iterations
+(S = 2 complex128 vectors, one Gram-Schmidt pass, fused H application), summed over
+the solves of one launch and divided by the launch's average duration (HIP events
+on the launch stream).  cpu_baseline: the CPU oracle timed on one host core over a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-point·steps/s at 1e-10 error, 8th order; adjoint grads/s; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+DT_STAR = 10.0
+N = 2048
+ORDER, SCHEME, METHOD = 8, "suzuki", "midp"
+TOL = 1e-14
+
+
+def alg_bytes(n: int, st) -> float:
+    """32 (I^2 + 4I + 8) bytes per grid point per solve, summed over the solves."""
+    return 32.0 * n * (st.iterations_sq + 4 * st.iterations + 8 * st.solves)
+
+
+def cpu_leg(seconds: float = 15.0) -> dict:
+    """Oracle on one core: the first packet of the batch, SZ-8 steps of dt* until ~seconds."""
+    code = f"""
+import sys, time, json
+sys.path.insert(0, {ROOT!r})
+import oracle as O
+from paper_1902_04661_amd import inputs as I
+it = I.ragged_batch(1, seed=0, fixed_n={N})[0]
+m = O.model_from_item(it)
+opts = O.SolverOpts(tol={TOL}, restart=32)
+psi = it.psi0
+t0 = time.time(); steps = 0
+while True:
+    psi = O.propagate(m, psi, O.MIDP, O.SUZUKI, {ORDER}, {DT_STAR}, 1, opts)
+    steps += 1
+    if time.time() - t0 > {seconds} or steps >= 400:
+        break
+el = time.time() - t0
+print(json.dumps(dict(steps=steps, seconds=el)))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": N * r["steps"] / r["seconds"], "unit": "grid-point·steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"1 packet, N={N}, {r['steps']} SZ-8 steps of dt={DT_STAR} in {r['seconds']:.1f} s "
+                      f"(numpy FP64, one thread)"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--single-steps", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs each batch on a single MI355X "
+              "(multi-GPU sharding is described in the design notes, not run).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1902_04661_amd import gqd, inputs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    opts = gqd.SolverOpts(tol=TOL, restart=32)
+
+    # ---------------------------------------------------------------- batched run
+    items = inputs.ragged_batch(args.batch, seed=0, fixed_n=N)
+    prop = gqd.from_items(items, device=dev)
+    psi0 = prop.pack([it.psi0 for it in items])
+    psi = psi0.clone()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        prop.propagate(psi, METHOD, SCHEME, ORDER, DT_STAR, 1, opts)
+    print(f"[bench] warmup {args.warmup} steps done, batch {args.batch}", file=sys.stderr, flush=True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    bytes_total = 0.0
+    iters = iters_sq = solves = applies = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        st = prop.propagate(psi, METHOD, SCHEME, ORDER, DT_STAR, 1, opts)   # one launch
+        ends[k].record(stream)
+        bytes_total += alg_bytes(N, st)
+        iters += st.iterations
+        iters_sq += st.iterations_sq
+        solves += st.solves
+        applies += st.h_applies
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    avg_kernel_s = sum(kern_ms) / len(kern_ms) / 1e3
+    value = args.batch * N * args.steps / wall
+    achieved = bytes_total / args.steps / avg_kernel_s / 1e9
+    print(f"[bench] timed {args.steps} steps: {wall:.2f} s wall, kernel {avg_kernel_s * 1e3:.1f} ms/step, "
+          f"mean GMRES iterations {iters / solves:.2f}", file=sys.stderr, flush=True)
+
+    # conservation check on the batch (outside the timed region)
+    check = {}
+    if not args.no_check:
+        d0 = prop.diag(psi0).cpu().numpy()
+        d1 = prop.diag(psi).cpu().numpy()
+        check = {"max_norm_drift": float(np.max(np.abs(d1[:, 0] - d0[:, 0]))),
+                 "max_energy_drift": float(np.max(np.abs(d1[:, 1] - d0[:, 1])))}
+
+    # ------------------------------------------------------------- single packet
+    single = {}
+    if args.single_steps > 0:
+        it = inputs.nai_like_item(N)
+        p1 = gqd.from_items([it], device=dev)
+        s1 = p1.pack([it.psi0])
+        p1.propagate(s1, METHOD, SCHEME, ORDER, DT_STAR, 1, opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st1 = p1.propagate(s1, METHOD, SCHEME, ORDER, DT_STAR, args.single_steps, opts)
+        torch.cuda.synchronize()
+        el1 = time.perf_counter() - t1
+        single = {"value": N * args.single_steps / el1, "unit": "grid-point·steps/s",
+                  "ms_per_step": 1e3 * el1 / args.single_steps,
+                  "mean_gmres_iterations": st1.iterations / max(st1.solves, 1),
+                  "us_per_h_apply": 1e6 * el1 / max(st1.h_applies, 1),
+                  "workload": f"one packet q0=5 p0=0 w=0.12, N={N}, SZ-8 midpoint, dt={DT_STAR}"}
+        print(f"[bench] single packet: {single['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_leg()
+        print(f"[bench] cpu oracle: {cpu['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point·steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"nai2048_sz8_midpoint_dt10_batch{args.batch}",
+                   "model": "two-surface NaI-like adiabatic model, N=2048 on [3,16) bohr",
+                   "batch": args.batch, "n": N, "method": "implicit midpoint", "scheme": "suzuki",
+                   "order": ORDER, "dt": DT_STAR, "gmres_tol": TOL, "restart": 32,
+                   "substeps_per_step": 125, "parallelism": "one workgroup per wavepacket"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_run<2048> (propagate)",
+                     "alg_bytes_per_launch": bytes_total / args.steps,
+                     "avg_launch_ms": avg_kernel_s * 1e3},
+        "cpu_baseline": cpu,
+        "single_packet": single,
+        "gmres": {"mean_iterations": iters / solves, "h_applies_per_step": applies / args.steps,
+                  "solves_per_step": solves / args.steps},
+        "check": check,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -85,6 +85,7 @@ typedef struct {
 typedef struct {
   long long h_applies;  /* H applications, all items */
   long long iterations; /* Arnoldi iterations, all items */
+  long long iterations_sq; /* sum over solves of the squared iteration count */
   long long solves;     /* GMRES solves, all items */
   int max_iters;        /* largest iteration count of one solve */
   int failures;         /* solves that hit maxit */
@@ -103,7 +104,7 @@ void gqd_destroy(gqd_handle* h);
 gqd_status gqd_state_size(const gqd_handle* h, long long* n_complex);
 gqd_status gqd_state_offset(const gqd_handle* h, int item, long long* offset);
 
-/* Workspace for the solver: (restart + 5) state vectors.  The caller allocates it
+/* Workspace for the solver: (restart + 6) state vectors.  The caller allocates it
  * (bytes from gqd_workspace_size) and passes it once; it must stay valid. */
 gqd_status gqd_workspace_size(const gqd_handle* h, const gqd_solver_opts* o, size_t* bytes);
 gqd_status gqd_set_workspace(gqd_handle* h, void* dev_ptr, size_t bytes);
@@ -126,6 +127,13 @@ gqd_status gqd_implicit_step(gqd_handle* h, gqd_method m, double dt, void* psi,
 gqd_status gqd_propagate(gqd_handle* h, gqd_method m, gqd_scheme s, int order, double dt,
                          long long nsteps, void* psi, const gqd_solver_opts* o,
                          gqd_stats* st, void* stream);
+
+/* As gqd_propagate, but item b takes its own step dt[b] and step count nsteps[b]
+ * (DEVICE arrays of length batch; a negative dt propagates backward).  One launch
+ * covers the whole batch, so items with different steps run side by side. */
+gqd_status gqd_propagate_items(gqd_handle* h, gqd_method m, gqd_scheme s, int order,
+                               const double* dt, const long long* nsteps, void* psi,
+                               const gqd_solver_opts* o, gqd_stats* st, void* stream);
 
 /* Reverse sweep of gqd_propagate for a real loss L(psi(T)), with no stored
  * trajectory: every substep's Cayley map is inverted exactly (time reversibility,

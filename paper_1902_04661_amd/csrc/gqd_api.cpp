@@ -170,6 +170,7 @@ gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
     const ItemStats& s = h->h_stats[b];
     st->h_applies += s.h_applies;
     st->iterations += s.iterations;
+    st->iterations_sq += s.iterations_sq;
     st->solves += s.solves;
     if (s.max_iters > st->max_iters) st->max_iters = s.max_iters;
     st->failures += s.failures;
@@ -339,9 +340,9 @@ gqd_status gqd_apply_H(gqd_handle* h, const void* in, void* out, void* stream) {
   return for_each_class(h, (hipStream_t)stream, a, launch_apply_h);
 }
 
-gqd_status gqd_propagate(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, double dt,
-                         long long nsteps, void* psi, const gqd_solver_opts* o, gqd_stats* st,
-                         void* stream) {
+static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, double dt,
+                                 long long nsteps, const double* dt_item, const long long* nsteps_item,
+                                 void* psi, const gqd_solver_opts* o, gqd_stats* st, void* stream) {
   gqd_status s = ready(h, true, o);
   if (s != GQD_OK) return s;
   if (!psi) return fail(GQD_ERR_INVALID, "NULL state pointer");
@@ -354,15 +355,30 @@ gqd_status gqd_propagate(gqd_handle* h, gqd_method m, gqd_scheme sch, int order,
   a.psi = (double2*)psi;
   a.work = (double2*)h->work;
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+  a.mode = 0;
   a.method = (m == GQD_TRAP) ? kTrap : kMidp;
   a.dt = dt;
   a.nsteps = nsteps;
+  a.dt_item = dt_item;
+  a.nsteps_item = nsteps_item;
   a.hpsi_valid = 0;
   hipStream_t strm = (hipStream_t)stream;
-  a.mode = 0;
   s = for_each_class(h, strm, a, launch_run);
   if (s != GQD_OK) return s;
   return st ? collect_stats(h, strm, st) : GQD_OK;
+}
+
+gqd_status gqd_propagate(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, double dt,
+                         long long nsteps, void* psi, const gqd_solver_opts* o, gqd_stats* st,
+                         void* stream) {
+  return propagate_impl(h, m, sch, order, dt, nsteps, nullptr, nullptr, psi, o, st, stream);
+}
+
+gqd_status gqd_propagate_items(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, const double* dt,
+                               const long long* nsteps, void* psi, const gqd_solver_opts* o,
+                               gqd_stats* st, void* stream) {
+  if (!dt || !nsteps) return fail(GQD_ERR_INVALID, "NULL per-item dt or nsteps");
+  return propagate_impl(h, m, sch, order, 0.0, 0, dt, nsteps, psi, o, st, stream);
 }
 
 gqd_status gqd_implicit_step(gqd_handle* h, gqd_method m, double dt, void* psi, const gqd_solver_opts* o,

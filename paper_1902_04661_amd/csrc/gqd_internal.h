@@ -29,6 +29,7 @@ struct ItemMeta {
 struct ItemStats {
   long long h_applies;
   long long iterations;
+  long long iterations_sq;  // sum over solves of (iterations of the solve)^2
   int solves;
   int max_iters;
   int failures;         // solves that hit maxit
@@ -75,6 +76,8 @@ struct KArgs {
   int method;
   double dt;
   long long nsteps;
+  const double* dt_item;        // optional per-item step (device), overrides dt
+  const long long* nsteps_item; // optional per-item step count (device), overrides nsteps
   GammaTab gt;
   int hpsi_valid;       // trapezoid economy: HPSI slot already holds H psi
   ItemStats* stats;

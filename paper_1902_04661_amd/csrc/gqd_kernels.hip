@@ -401,9 +401,11 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
   double2* CHI = S3 + E::VEC;                      // inner A x of an H application
   const bool adj = a.mode == 1;
   const bool midp = a.method == kMidp;
+  const double dt = a.dt_item ? uniform_d(a.dt_item[item]) : a.dt;
+  const long long nsteps = a.nsteps_item ? a.nsteps_item[item] : a.nsteps;
   const bool literal = a.sc.literal != 0;
 
-  long long napply = 0, iters_total = 0;
+  long long napply = 0, iters_total = 0, iters_sq = 0;
   int solves = 0, max_iters = 0, failures = 0;
   bool bad = false;
   bool have_hpsi = a.hpsi_valid != 0;
@@ -449,6 +451,7 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
   auto solve_end = [&](bool conv) {
     ++solves;
     iters_total += iters;
+    iters_sq += (long long)iters * iters;
     if (iters > max_iters) max_iters = iters;
     if (!conv) ++failures;
     pc = after;
@@ -483,8 +486,8 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
     }
     switch (pc) {
       case kSubstep: {
-        if (n >= a.nsteps) goto done;
-        alpha = 0.5 * (substep_tau(cc, a.gt) * a.dt);
+        if (n >= nsteps) goto done;
+        alpha = 0.5 * (substep_tau(cc, a.gt) * dt);
         if (adj) {
           solve_begin(psi, S0, -alpha, kAdjAfterPhi);
         } else if (midp) {
@@ -721,6 +724,7 @@ done:
     ItemStats* st = a.stats + item;
     st->h_applies = napply;
     st->iterations = iters_total;
+    st->iterations_sq = iters_sq;
     st->solves = solves;
     st->max_iters = max_iters;
     st->failures = failures;

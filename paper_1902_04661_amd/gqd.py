@@ -50,6 +50,7 @@ class _SolverOpts(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("h_applies", ctypes.c_longlong), ("iterations", ctypes.c_longlong),
+                ("iterations_sq", ctypes.c_longlong),
                 ("solves", ctypes.c_longlong), ("max_iters", ctypes.c_int),
                 ("failures", ctypes.c_int), ("failed_item", ctypes.c_int),
                 ("nonfinite", ctypes.c_int)]
@@ -79,6 +80,7 @@ def load_library(path: str = LIB_PATH):
         "gqd_apply_H": ([vp, vp, vp, vp], i),
         "gqd_implicit_step": ([vp, i, d, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
         "gqd_propagate": ([vp, i, i, i, d, ll, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
+        "gqd_propagate_items": ([vp, i, i, i, vp, vp, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
         "gqd_adjoint": ([vp, i, i, d, ll, vp, vp, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
         "gqd_diag": ([vp, vp, vp, vp], i),
         "gqd_inner": ([vp, vp, vp, vp, vp], i),
@@ -95,7 +97,8 @@ def load_library(path: str = LIB_PATH):
 def exported_symbols() -> List[str]:
     return ["gqd_create", "gqd_destroy", "gqd_state_size", "gqd_state_offset",
             "gqd_workspace_size", "gqd_set_workspace", "gqd_set_surfaces", "gqd_apply_H",
-            "gqd_implicit_step", "gqd_propagate", "gqd_adjoint", "gqd_diag", "gqd_inner",
+            "gqd_implicit_step", "gqd_propagate", "gqd_propagate_items", "gqd_adjoint",
+            "gqd_diag", "gqd_inner",
             "gqd_last_error"]
 
 
@@ -122,11 +125,19 @@ class SolverOpts:
 class Stats:
     h_applies: int
     iterations: int
+    iterations_sq: int
     solves: int
     max_iters: int
     failures: int
     failed_item: int
     nonfinite: int
+
+
+def _stats(st) -> Optional[Stats]:
+    if st is None:
+        return None
+    return Stats(st.h_applies, st.iterations, st.iterations_sq, st.solves, st.max_iters,
+                 st.failures, st.failed_item, st.nonfinite)
 
 
 def _stream_ptr(stream=None):
@@ -241,8 +252,25 @@ class Propagator:
         _check(_lib.gqd_propagate(self._h, _METHODS[method], _SCHEMES[scheme], int(order), float(dt),
                                   int(nsteps), self._state(psi), ctypes.byref(co),
                                   ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
-        return Stats(st.h_applies, st.iterations, st.solves, st.max_iters, st.failures,
-                     st.failed_item, st.nonfinite) if st is not None else None
+        return _stats(st)
+
+    def propagate_items(self, psi: torch.Tensor, method="midp", scheme="suzuki", order: int = 2,
+                        dt=None, nsteps=None, opts: Optional[SolverOpts] = None,
+                        stats: bool = True, stream=None) -> Optional[Stats]:
+        """In place, item b takes nsteps[b] composed steps of dt[b] (one launch)."""
+        opts = opts or SolverOpts()
+        self._ensure_workspace(opts)
+        dt_t = torch.as_tensor(np.asarray(dt, dtype=np.float64).reshape(self.batch)).to(self.device)
+        ns_t = torch.as_tensor(np.asarray(nsteps, dtype=np.int64).reshape(self.batch)).to(self.device)
+        co = opts.c()
+        st = _Stats() if stats else None
+        _check(_lib.gqd_propagate_items(self._h, _METHODS[method], _SCHEMES[scheme], int(order),
+                                        ctypes.c_void_p(dt_t.data_ptr()), ctypes.c_void_p(ns_t.data_ptr()),
+                                        self._state(psi), ctypes.byref(co),
+                                        ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
+        if st is None:
+            self._keep = (dt_t, ns_t)  # alive until the caller synchronises
+        return _stats(st)
 
     def implicit_step(self, psi: torch.Tensor, method="midp", dt: float = 1.0,
                       opts: Optional[SolverOpts] = None, stats: bool = True, stream=None):
@@ -252,8 +280,7 @@ class Propagator:
         st = _Stats() if stats else None
         _check(_lib.gqd_implicit_step(self._h, _METHODS[method], float(dt), self._state(psi), ctypes.byref(co),
                                       ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
-        return Stats(st.h_applies, st.iterations, st.solves, st.max_iters, st.failures,
-                     st.failed_item, st.nonfinite) if st is not None else None
+        return _stats(st)
 
     def adjoint(self, psi: torch.Tensor, lam: torch.Tensor, gF: torch.Tensor, scheme="suzuki",
                 order: int = 2, dt: float = 1.0, nsteps: int = 1, opts: Optional[SolverOpts] = None,
@@ -269,8 +296,7 @@ class Propagator:
                                 self._state(psi), self._state(lam), ctypes.c_void_p(gF.data_ptr()),
                                 ctypes.byref(co), ctypes.byref(st) if st is not None else None,
                                 _stream_ptr(stream)))
-        return Stats(st.h_applies, st.iterations, st.solves, st.max_iters, st.failures,
-                     st.failed_item, st.nonfinite) if st is not None else None
+        return _stats(st)
 
     def diag(self, psi: torch.Tensor, stream=None) -> torch.Tensor:
         """(batch, 4): norm, energy, population of surface 1, of surface 2."""
