@@ -11,21 +11,36 @@
 
 namespace gqd {
 
+// Address-space qualified pointers: global memory (1) and LDS (3).  Generic pointers
+// would compile to flat instructions.
+#define GQD_G __attribute__((address_space(1)))
+#define GQD_L __attribute__((address_space(3)))
+
+// Complex value: a native two-double vector (loads and stores from any address space
+// as one 16-byte access).  Memory layout equals interleaved complex128.
+typedef double cplx __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cplx mk(double re, double im) {
+  cplx r;
+  r.x = re;
+  r.y = im;
+  return r;
+}
+
 // ----------------------------------------------------------------- complex helpers
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return mk(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return mk(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 // conj(a) * b
-__device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+__device__ __forceinline__ cplx cconjmul(cplx a, cplx b) {
+  return mk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return mk(a.x * s, a.y * s); }
 // i * s * a
-__device__ __forceinline__ double2 cmul_is(double2 a, double s) { return make_double2(-s * a.y, s * a.x); }
-__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
-__device__ __forceinline__ double2 cneg(double2 a) { return make_double2(-a.x, -a.y); }
+__device__ __forceinline__ cplx cmul_is(cplx a, double s) { return mk(-s * a.y, s * a.x); }
+__device__ __forceinline__ double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ cplx cneg(cplx a) { return mk(-a.x, -a.y); }
 
 // ------------------------------------------------------------------- DFT butterflies
 // X_k = sum_r x_r exp(S * 2 pi i r k / R), natural order in and out; S = -1 forward.
@@ -38,38 +53,38 @@ struct TwC {
 
 // multiply z by exp(S * 2 pi i K / R) for constant K, R (R <= 16)
 template <int R, int S, int K>
-__device__ __forceinline__ double2 twc(double2 z) {
+__device__ __forceinline__ cplx twc(cplx z) {
   constexpr int k16 = K * (16 / R);  // angle in units of 2 pi / 16, 0..7
   if constexpr (k16 == 0) {
     return z;
   } else if constexpr (k16 == 4) {  // multiply by S*i
-    return S > 0 ? make_double2(-z.y, z.x) : make_double2(z.y, -z.x);
+    return S > 0 ? mk(-z.y, z.x) : mk(z.y, -z.x);
   } else if constexpr (k16 == 2 || k16 == 6) {
     // (cos, S sin) with cos = +-C8, sin = C8
     constexpr double c = (k16 == 2) ? TwC::C8 : -TwC::C8;
     constexpr double s = S * TwC::C8;
-    return make_double2(c * z.x - s * z.y, c * z.y + s * z.x);
+    return mk(c * z.x - s * z.y, c * z.y + s * z.x);
   } else {
     constexpr double c = (k16 == 1) ? TwC::C16 : (k16 == 3) ? TwC::S16 : (k16 == 5) ? -TwC::S16 : -TwC::C16;
     constexpr double s0 = (k16 == 1) ? TwC::S16 : (k16 == 3) ? TwC::C16 : (k16 == 5) ? TwC::C16 : TwC::S16;
     constexpr double s = S * s0;
-    return make_double2(c * z.x - s * z.y, c * z.y + s * z.x);
+    return mk(c * z.x - s * z.y, c * z.y + s * z.x);
   }
 }
 
 template <int R, int S>
 struct DFT {
   template <int K>
-  static __device__ __forceinline__ void combine(double2* x, const double2* e, const double2* o) {
+  static __device__ __forceinline__ void combine(cplx* x, const cplx* e, const cplx* o) {
     if constexpr (K < R / 2) {
-      double2 t = twc<R, S, K>(o[K]);
+      cplx t = twc<R, S, K>(o[K]);
       x[K] = cadd(e[K], t);
       x[K + R / 2] = csub(e[K], t);
       combine<K + 1>(x, e, o);
     }
   }
-  static __device__ __forceinline__ void run(double2* x) {
-    double2 e[R / 2], o[R / 2];
+  static __device__ __forceinline__ void run(cplx* x) {
+    cplx e[R / 2], o[R / 2];
 #pragma unroll
     for (int i = 0; i < R / 2; ++i) {
       e[i] = x[2 * i];
@@ -82,30 +97,33 @@ struct DFT {
 };
 template <int S>
 struct DFT<2, S> {
-  static __device__ __forceinline__ void run(double2* x) {
-    double2 a = x[0], b = x[1];
+  static __device__ __forceinline__ void run(cplx* x) {
+    cplx a = x[0], b = x[1];
     x[0] = cadd(a, b);
     x[1] = csub(a, b);
   }
 };
 template <int S>
 struct DFT<1, S> {
-  static __device__ __forceinline__ void run(double2*) {}
+  static __device__ __forceinline__ void run(cplx*) {}
 };
 
 // Returns p unchanged but opaque to the optimiser, so loads through it cannot be
 // hoisted out of the enclosing loop (loop-invariant twiddle and coefficient loads
 // would otherwise stay live in registers for the whole kernel).
 template <class Tp>
-__device__ __forceinline__ Tp* opaque(Tp* p) {
+__device__ __forceinline__ GQD_G Tp* opaque(Tp* p) {
   // every pointer passed here is the same in all lanes: broadcast it to a scalar
   // register first (free when the compiler already knows it is uniform)
   const unsigned long long b = reinterpret_cast<unsigned long long>(p);
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(b & 0xffffffffull));
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
-  p = reinterpret_cast<Tp*>(((unsigned long long)hi << 32) | lo);
-  asm volatile("" : "+s"(p));
-  return p;
+  unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(b & 0xffffffffull));
+  unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  asm volatile("" : "+s"(lo), "+s"(hi));
+  return (GQD_G Tp*)(((unsigned long long)hi << 32) | lo);
+}
+template <class Tp>
+__device__ __forceinline__ GQD_G Tp* opaque(GQD_G Tp* p) {
+  return opaque((Tp*)p);
 }
 // Same for a uniform double and for the lane index: values derived from them
 // (addresses, per-lane scale factors) are recomputed where used instead of being
@@ -142,20 +160,20 @@ constexpr int TW_N = 4096;  // twiddle table: exp(-2 pi i k / 4096), k < 4096
 
 // Twiddle exp(S * 2 pi i * num / den) for den | TW_N, from the table.
 template <int S>
-__device__ __forceinline__ double2 tw_lookup(const double2* __restrict__ tw, int idx4096) {
-  double2 w = tw[idx4096];
-  return S < 0 ? w : make_double2(w.x, -w.y);
+__device__ __forceinline__ cplx tw_lookup(const GQD_G cplx* __restrict__ tw, int idx4096) {
+  cplx w = tw[idx4096];
+  return S < 0 ? w : mk(w.x, -w.y);
 }
 
 // One in-place Stockham pass over 2 sequences of length N in LDS (seq s at lds[s*N]).
 // Butterfly j (< N/R) of sequence s reads x[j + r N/R], twiddles by w_{Ns R}^{r k}
 // (k = j mod Ns), applies the radix-R DFT and writes y[(j/Ns) Ns R + k + r Ns].
 template <int N, int T, int R, int Ns, int S>
-__device__ __forceinline__ void stockham_lds(double2* lds, const double2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_lds(GQD_L cplx* lds, const GQD_G cplx* __restrict__ tw) {
   constexpr int NB = 2 * N / R;
   static_assert(NB % T == 0, "butterflies must be a multiple of the thread count");
   constexpr int PER = NB / T;
-  double2 x[PER][R];
+  cplx x[PER][R];
   int tid = lane_tid();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {

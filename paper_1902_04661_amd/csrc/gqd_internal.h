@@ -83,11 +83,15 @@ struct KArgs {
   ItemStats* stats;
 };
 
+// Sizes up to this one keep the input / partial result of an H application in LDS.
+constexpr int kParkMaxN = 2048;
+
 // LDS bytes needed by a launch at size N with restart length m.
 inline size_t lds_bytes(int N, int m) {
   const int T = (N == 4096) ? 512 : (N / 4);  // threads per item (N / R0 of the plan)
   const int W = T / 64;
-  const size_t c = 2 * (size_t)N + (size_t)W * (m + 1) + 2 * (m + 1) + 2 * (size_t)m +
+  const size_t park = (N <= kParkMaxN) ? 2 * (size_t)N : 0;
+  const size_t c = 2 * (size_t)N + park + (size_t)W * (m + 1) + 2 * (m + 1) + 2 * (size_t)m +
                    (size_t)m * (m + 1) / 2;
   return c * 16 + (size_t)m * 8 + 16 * 8;
 }

@@ -20,25 +20,28 @@ struct Eng {
   static_assert(T % 64 == 0, "whole waves only");
   static constexpr int RF = (R3 == 1) ? R2 : R3;  // radix of the fused k-space pass
   static constexpr size_t VEC = 2 * (size_t)N;    // complex elements of one state vector
+  static constexpr bool kPark = N <= kParkMaxN;     // H-application scratch in LDS
 
   struct OV {
-    double2 v[2][R0];
+    cplx v[2][R0];
   };
 
+  using LP = GQD_L cplx*;
   struct Ctx {
-    double2* fft;   // [2N]
-    double2* part;  // [W][kmax]
-    double2* hcol;  // [kmax]
-    double2* g;     // [kmax]
-    double2* sn;    // [m]
-    double2* y;     // [m]
-    double2* R;     // [m(m+1)/2], column j at j(j+1)/2
-    double* cs;     // [m]
-    double* scal;   // [16]
+    GQD_L cplx* fft;   // [2N]
+    GQD_L cplx* park;  // [2N] LDS scratch at owned points when kPark, else null
+    GQD_L cplx* part;  // [W][kmax]
+    GQD_L cplx* hcol;  // [kmax]
+    GQD_L cplx* g;     // [kmax]
+    GQD_L cplx* sn;    // [m]
+    GQD_L cplx* y;     // [m]
+    GQD_L cplx* R;     // [m(m+1)/2], column j at j(j+1)/2
+    GQD_L double* cs;     // [m]
+    GQD_L double* scal;   // [16]
     int kmax;
     const double* V;   // item's V, [2][N]
     const double* F;   // item's F12, [N]
-    const double2* tw;
+    const cplx* tw;
     double pscale;
     double inv2m;
   };
@@ -46,37 +49,38 @@ struct Eng {
   // owned point r of this lane; lane_tid() keeps address arithmetic local to its use
   static __device__ __forceinline__ int pt(int r) { return lane_tid() + r * T; }
 
-  static __device__ Ctx make_ctx(double2* smem, int m, const KArgs& a, const ItemMeta& im) {
+  static __device__ Ctx make_ctx(GQD_L cplx* smem, int m, const KArgs& a, const ItemMeta& im) {
     Ctx c;
     const int kmax = m + 1;
     c.kmax = kmax;
     c.fft = smem;
-    c.part = c.fft + 2 * N;
+    c.park = kPark ? c.fft + 2 * N : nullptr;
+    c.part = c.fft + (kPark ? 4 : 2) * N;
     c.hcol = c.part + W * kmax;
     c.g = c.hcol + kmax;
     c.sn = c.g + kmax;
     c.y = c.sn + m;
     c.R = c.y + m;
-    c.cs = reinterpret_cast<double*>(c.R + (m * (m + 1)) / 2);
+    c.cs = (GQD_L double*)(c.R + (m * (m + 1)) / 2);
     c.scal = c.cs + m;
     c.V = a.V + im.voff;
     c.F = a.F + im.foff;
-    c.tw = a.tw;
+    c.tw = (const cplx*)a.tw;
     c.pscale = im.pscale;
     c.inv2m = a.inv2m;
     return c;
   }
 
   // ------------------------------------------------------------ owned-point vectors
-  static __device__ __forceinline__ void load(OV& x, const double2* __restrict__ g) {
-    g = opaque(g);
+  static __device__ __forceinline__ void load(OV& x, const cplx* __restrict__ gp) {
+    const GQD_G cplx* g = opaque(gp);
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int r = 0; r < R0; ++r) x.v[s][r] = g[s * N + pt(r)];
   }
-  static __device__ __forceinline__ void store(const OV& x, double2* __restrict__ g) {
-    g = opaque(g);
+  static __device__ __forceinline__ void store(const OV& x, cplx* __restrict__ gp) {
+    GQD_G cplx* g = opaque(gp);
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -95,7 +99,7 @@ struct Eng {
   // Workgroup sum of one real; every thread returns the same value (same order).
   static __device__ double block_sum1(double v, const Ctx& c) {
     v = wave_sum(v);
-    double* p = reinterpret_cast<double*>(c.part);
+    GQD_L double* p = (GQD_L double*)c.part;
     if ((threadIdx.x & 63) == 0) p[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
@@ -106,29 +110,35 @@ struct Eng {
   }
 
   // dst[i] = sum conj(V_i) w over the item, i < K (V_i = basis + i*VEC); dst in LDS.
-  static __device__ void block_dots(const double2* __restrict__ basis, const OV& w, int K,
-                                    const Ctx& c, double2* dst) {
+  // With with_norm, dst[K] = (||w||^2, 0) comes out of the same reduction.
+  static __device__ void block_dots(const cplx* __restrict__ basis, const OV& w, int K,
+                                    const Ctx& c, GQD_L cplx* dst, bool with_norm = false) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (with_norm) {
+      const double nn = wave_sum(norm2(w));
+      if (lane == 0) c.part[wv * c.kmax + K] = mk(nn, 0.0);
+    }
 #pragma unroll 1
     for (int i = 0; i < K; ++i) {
-      const double2* Vi = opaque(basis + (size_t)i * VEC);
+      const GQD_G cplx* Vi = opaque(basis + (size_t)i * VEC);
       double ax = 0.0, ay = 0.0;
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-          const double2 b = Vi[s * N + pt(r)];
-          const double2 z = w.v[s][r];
+          const cplx b = Vi[s * N + pt(r)];
+          const cplx z = w.v[s][r];
           ax += b.x * z.x + b.y * z.y;
           ay += b.x * z.y - b.y * z.x;
         }
       ax = wave_sum(ax);
       ay = wave_sum(ay);
-      if (lane == 0) c.part[wv * c.kmax + i] = make_double2(ax, ay);
+      if (lane == 0) c.part[wv * c.kmax + i] = mk(ax, ay);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < K; i += T) {
-      double2 s = make_double2(0.0, 0.0);
+    const int Kt = with_norm ? K + 1 : K;
+    for (int i = threadIdx.x; i < Kt; i += T) {
+      cplx s = mk(0.0, 0.0);
 #pragma unroll
       for (int w2 = 0; w2 < W; ++w2) s = cadd(s, c.part[w2 * c.kmax + i]);
       dst[i] = s;
@@ -137,11 +147,11 @@ struct Eng {
   }
 
   // w -= sum_i h[i] V_i, i < K (h in LDS)
-  static __device__ void block_axpy(const double2* __restrict__ basis, const double2* h, int K, OV& w) {
+  static __device__ void block_axpy(const cplx* __restrict__ basis, const GQD_L cplx* h, int K, OV& w) {
 #pragma unroll 1
     for (int i = 0; i < K; ++i) {
-      const double2* Vi = opaque(basis + (size_t)i * VEC);
-      const double2 hi = h[i];
+      const GQD_G cplx* Vi = opaque(basis + (size_t)i * VEC);
+      const cplx hi = h[i];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -153,12 +163,12 @@ struct Eng {
   // Fused last forward pass (radix RF, Ns = N/RF), momentum multiply and first
   // inverse pass (radix RF, Ns = 1): butterfly j's forward outputs are the k-space
   // points j + r N/RF, exactly the inputs of the inverse butterfly j.
-  static __device__ __forceinline__ void fused_kspace(const Ctx& c, const double2* tw) {
+  static __device__ __forceinline__ void fused_kspace(const Ctx& c, const GQD_G cplx* tw) {
     constexpr int NB = 2 * N / RF;
     static_assert(NB % T == 0, "fused pass butterflies");
     constexpr int PER = NB / T;
     constexpr int Ns = N / RF;
-    double2 x[PER][RF];
+    cplx x[PER][RF];
     int tid = lane_tid();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -193,11 +203,11 @@ struct Eng {
 
   // u = p x on both surfaces (forward DFT, multiply by p_k, inverse DFT / N).
   static __device__ void kinetic(const OV& x, OV& u, const Ctx& c) {
-    const double2* tw = opaque(c.tw);
+    const GQD_G cplx* tw = opaque(c.tw);
     // pass A: radix R0, Ns = 1, from owned registers (butterfly j = thread)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      double2 y[R0];
+      cplx y[R0];
 #pragma unroll
       for (int r = 0; r < R0; ++r) y[r] = x.v[s][r];
       DFT<R0, -1>::run(y);
@@ -221,7 +231,7 @@ struct Eng {
     constexpr int step = TW_N / N;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      double2 y[R0];
+      cplx y[R0];
 #pragma unroll
       for (int r = 0; r < R0; ++r) y[r] = c.fft[s * N + pt(r)];
 #pragma unroll
@@ -235,18 +245,18 @@ struct Eng {
 
   // y = [p - i F] x for x at xg (F12 couples surface 2 into surface 1, F21 = -F12).
   // The input is re-read at owned points after the transform.
-  static __device__ void apply_A(const double2* xg, OV& y, const Ctx& c) {
+  static __device__ void apply_A(const cplx* xg, OV& y, const Ctx& c) {
     {
       OV t;
       load(t, xg);
       kinetic(t, y, c);
     }
-    const double* F = opaque(c.F);
-    xg = opaque(xg);
+    const GQD_G double* F = opaque(c.F);
+    const GQD_G cplx* xq = opaque(xg);
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
       const double f = F[pt(r)];
-      const double2 x0 = xg[pt(r)], x1 = xg[N + pt(r)];
+      const cplx x0 = xq[pt(r)], x1 = xq[N + pt(r)];
       // -i f x2 added to surface 1, +i f x1 added to surface 2
       y.v[0][r] = cadd(y.v[0][r], cmul_is(x1, -f));
       y.v[1][r] = cadd(y.v[1][r], cmul_is(x0, f));
@@ -254,14 +264,62 @@ struct Eng {
   }
 
   // y <- y / (2m) + V x: completes H x = A (A x) / (2m) + V x after the second A pass.
-  static __device__ __forceinline__ void finish_H(OV& y, const double2* xg, const Ctx& c) {
-    const double* V = opaque(c.V);
-    xg = opaque(xg);
+  static __device__ __forceinline__ void finish_H(OV& y, const cplx* xg, const Ctx& c) {
+    const GQD_G double* V = opaque(c.V);
+    const GQD_G cplx* xq = opaque(xg);
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int r = 0; r < R0; ++r)
-        y.v[s][r] = cadd(cscale(y.v[s][r], c.inv2m), cscale(xg[s * N + pt(r)], V[s * N + pt(r)]));
+        y.v[s][r] = cadd(cscale(y.v[s][r], c.inv2m), cscale(xq[s * N + pt(r)], V[s * N + pt(r)]));
+  }
+
+  // Owned points of an LDS buffer (each lane only touches its own points).
+  static __device__ __forceinline__ void lds_store(const OV& x, GQD_L cplx* l) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) l[s * N + pt(r)] = x.v[s][r];
+  }
+
+  // y += -i F x on owned points (x at xs: LDS park or a global vector)
+  template <class P>
+  static __device__ __forceinline__ void couple(OV& y, P xs, const Ctx& c) {
+    const GQD_G double* F = opaque(c.F);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const double f = F[pt(r)];
+      const cplx x0 = xs[pt(r)], x1 = xs[N + pt(r)];
+      y.v[0][r] = cadd(y.v[0][r], cmul_is(x1, -f));
+      y.v[1][r] = cadd(y.v[1][r], cmul_is(x0, f));
+    }
+  }
+
+  // pre = (-i F chi) / (2m) + V x written to dst (LDS park or global), x read from xs;
+  // the outer A's coupling and the potential, formed before the second transform.
+  template <class P, class Q>
+  static __device__ __forceinline__ void make_pre(const OV& chi, P xs, Q dst, const Ctx& c) {
+    const GQD_G double* F = opaque(c.F);
+    const GQD_G double* V = opaque(c.V);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const double f = F[pt(r)];
+      const double v0 = V[pt(r)], v1 = V[N + pt(r)];
+      const cplx x0 = xs[pt(r)], x1 = xs[N + pt(r)];
+      const cplx p0 = cadd(cscale(cmul_is(chi.v[1][r], -f), c.inv2m), cscale(x0, v0));
+      const cplx p1 = cadd(cscale(cmul_is(chi.v[0][r], f), c.inv2m), cscale(x1, v1));
+      dst[pt(r)] = p0;
+      dst[N + pt(r)] = p1;
+    }
+  }
+
+  // y <- y / (2m) + pre
+  template <class P>
+  static __device__ __forceinline__ void add_pre(OV& y, P pre, const Ctx& c) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) y.v[s][r] = cadd(cscale(y.v[s][r], c.inv2m), pre[s * N + pt(r)]);
   }
 
   // --------------------------------------------------------------------- GMRES
@@ -269,41 +327,41 @@ struct Eng {
   // new rotation from (column[j], hn), stores column j of R and updates g.
   static __device__ void givens_update(int j, double hn, const Ctx& c) {
     if (threadIdx.x == 0) {
-      double2* h = c.hcol;
+      GQD_L cplx* h = c.hcol;
       for (int i = 0; i < j; ++i) {
         const double ci = c.cs[i];
-        const double2 si = c.sn[i];
-        const double2 hi = h[i], hi1 = h[i + 1];
-        const double2 t = cadd(cscale(hi, ci), cmul(si, hi1));
-        h[i + 1] = cadd(cmul(cneg(make_double2(si.x, -si.y)), hi), cscale(hi1, ci));
+        const cplx si = c.sn[i];
+        const cplx hi = h[i], hi1 = h[i + 1];
+        const cplx t = cadd(cscale(hi, ci), cmul(si, hi1));
+        h[i + 1] = cadd(cmul(cneg(mk(si.x, -si.y)), hi), cscale(hi1, ci));
         h[i] = t;
       }
-      const double2 a = h[j];
+      const cplx a = h[j];
       double cj;
-      double2 sj, rj;
+      cplx sj, rj;
       if (hn == 0.0) {
         cj = 1.0;
-        sj = make_double2(0.0, 0.0);
+        sj = mk(0.0, 0.0);
         rj = a;
       } else if (a.x == 0.0 && a.y == 0.0) {
         cj = 0.0;
-        sj = make_double2(1.0, 0.0);
-        rj = make_double2(hn, 0.0);
+        sj = mk(1.0, 0.0);
+        rj = mk(hn, 0.0);
       } else {
         const double absa = hypot(a.x, a.y);
         const double rho = sqrt(absa * absa + hn * hn);
-        const double2 ph = make_double2(a.x / absa, a.y / absa);
+        const cplx ph = mk(a.x / absa, a.y / absa);
         cj = absa / rho;
         sj = cscale(ph, hn / rho);
         rj = cscale(ph, rho);
       }
       c.cs[j] = cj;
       c.sn[j] = sj;
-      double2* Rj = c.R + (j * (j + 1)) / 2;
+      GQD_L cplx* Rj = c.R + (j * (j + 1)) / 2;
       for (int i = 0; i < j; ++i) Rj[i] = h[i];
       Rj[j] = rj;
-      const double2 gj = c.g[j];
-      c.g[j + 1] = cmul(cneg(make_double2(sj.x, -sj.y)), gj);
+      const cplx gj = c.g[j];
+      c.g[j + 1] = cmul(cneg(mk(sj.x, -sj.y)), gj);
       c.g[j] = cscale(gj, cj);
       c.scal[0] = hypot(c.g[j + 1].x, c.g[j + 1].y);
     }
@@ -314,12 +372,12 @@ struct Eng {
   static __device__ void back_solve(int k, const Ctx& c) {
     if (threadIdx.x == 0) {
       for (int i = k - 1; i >= 0; --i) {
-        double2 s = make_double2(0.0, 0.0);
+        cplx s = mk(0.0, 0.0);
         for (int l = i + 1; l < k; ++l) s = cadd(s, cmul(c.R[(l * (l + 1)) / 2 + i], c.y[l]));
-        const double2 num = csub(c.g[i], s);
-        const double2 d = c.R[(i * (i + 1)) / 2 + i];
+        const cplx num = csub(c.g[i], s);
+        const cplx d = c.R[(i * (i + 1)) / 2 + i];
         const double dd = d.x * d.x + d.y * d.y;
-        c.y[i] = make_double2((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd);
+        c.y[i] = mk((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd);
       }
     }
     __syncthreads();
@@ -385,20 +443,21 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
   constexpr int R0 = E::R0;
   constexpr int T = E::T;
   if ((int)blockIdx.x >= a.nlist) return;
-  extern __shared__ double2 smem[];
+  extern __shared__ double2 smem_raw[];
+  GQD_L cplx* smem = (GQD_L cplx*)smem_raw;
   const int item = a.list[blockIdx.x];
   const ItemMeta im = a.items[item];
   const int m = a.sc.m;
-  double2* work = a.work + im.off * (long long)(m + kWorkExtra);
+  cplx* work = (cplx*)a.work + im.off * (long long)(m + kWorkExtra);
   const auto c = E::make_ctx(smem, m, a, im);
-  double2* psi = a.psi + im.off;
-  double2* lam = a.aux + im.off;
-  double2* basis = work;
-  double2* S0 = work + (size_t)(m + 1) * E::VEC;  // X (solve output)  | PHI
-  double2* S1 = S0 + E::VEC;                       // B (rhs, H x)      | MU
-  double2* S2 = S1 + E::VEC;                       // HPSI              | A phi
-  double2* S3 = S2 + E::VEC;                       //                   | A mu
-  double2* CHI = S3 + E::VEC;                      // inner A x of an H application
+  cplx* psi = (cplx*)a.psi + im.off;
+  cplx* lam = (cplx*)a.aux + im.off;
+  cplx* basis = work;
+  cplx* S0 = work + (size_t)(m + 1) * E::VEC;  // X (solve output)  | PHI
+  cplx* S1 = S0 + E::VEC;                       // B (rhs, H x)      | MU
+  cplx* S2 = S1 + E::VEC;                       // HPSI              | A phi
+  cplx* S3 = S2 + E::VEC;                       //                   | A mu
+  cplx* CHI = S3 + E::VEC;                      // inner A x of an H application
   const bool adj = a.mode == 1;
   const bool midp = a.method == kMidp;
   const double dt = a.dt_item ? uniform_d(a.dt_item[item]) : a.dt;
@@ -417,24 +476,24 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
   // operator request
   bool pending = false, opH = false;
   int half = 0;
-  const double2* opsrc = nullptr;
+  const cplx* opsrc = nullptr;
   // solve state
-  const double2* bg = nullptr;
-  double2* xg = nullptr;
+  const cplx* bg = nullptr;
+  cplx* xg = nullptr;
   double al = 0.0, tolb = 0.0;
   int j = 0, iters = 0, after = kSubstep;
 
   int pc = kSubstep;
   OV y;
 
-  auto request = [&](const double2* src, bool h) {
+  auto request = [&](const cplx* src, bool h) {
     pending = true;
     opsrc = src;
     opH = h;
     half = 0;
   };
   // start a solve of (1 + i al H) x = b: ||b||, then ask for H b
-  auto solve_begin = [&](const double2* b, double2* x, double alv, int ret) {
+  auto solve_begin = [&](const cplx* b, cplx* x, double alv, int ret) {
     bg = b;
     xg = x;
     al = alv;
@@ -472,14 +531,35 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
   for (;;) {
     if (bad) break;
     if (pending) {
-      E::apply_A(half == 0 ? opsrc : CHI, y, c);
-      if (opH && half == 0) {
-        E::store(y, CHI);
-        half = 1;
-        continue;
+      // one transform per turn: turn 1 takes the input from opsrc, turn 2 (H only) takes
+      // chi = A x from registers; x and the partial result live in the park buffer
+      // (LDS, N <= 2048) or in the CHI slot (global, larger N)
+      OV t;
+      if (half == 0) {
+        E::load(t, opsrc);
+        if constexpr (E::kPark) E::lds_store(t, c.park);
+      } else {
+        t = y;
       }
-      if (opH) {
-        E::finish_H(y, opsrc, c);
+      E::kinetic(t, y, c);
+      if (half == 0) {
+        if constexpr (E::kPark) {
+          E::couple(y, c.park, c);
+          if (opH) E::make_pre(y, c.park, c.park, c);
+        } else {
+          E::couple(y, opaque(opsrc), c);
+          if (opH) E::make_pre(y, opaque(opsrc), opaque(CHI), c);
+        }
+        if (opH) {
+          half = 1;
+          continue;
+        }
+      } else {
+        if constexpr (E::kPark) {
+          E::add_pre(y, c.park, c);
+        } else {
+          E::add_pre(y, opaque(CHI), c);
+        }
         ++napply;
       }
       pending = false;
@@ -527,8 +607,8 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
           for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
-              const double2 d = csub(p.v[s][r], q.v[s][r]);
-              q.v[s][r] = make_double2(d.y / alpha, -d.x / alpha);
+              const cplx d = csub(p.v[s][r], q.v[s][r]);
+              q.v[s][r] = mk(d.y / alpha, -d.x / alpha);
             }
           E::store(q, S2);
           have_hpsi = true;
@@ -604,9 +684,9 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-          for (int r = 0; r < R0; ++r) y.v[s][r] = make_double2(y.v[s][r].x / beta, y.v[s][r].y / beta);
+          for (int r = 0; r < R0; ++r) y.v[s][r] = mk(y.v[s][r].x / beta, y.v[s][r].y / beta);
         E::store(y, basis);
-        if (threadIdx.x == 0) c.g[0] = make_double2(beta, 0.0);
+        if (threadIdx.x == 0) c.g[0] = mk(beta, 0.0);
         // (the next block reduction's barrier orders this write before any read)
         j = 0;
         request(basis, true);
@@ -614,7 +694,7 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
         break;
       }
       case kSolveArnoldi: {
-        const double2* Vj = basis + (size_t)j * E::VEC;
+        const cplx* Vj = basis + (size_t)j * E::VEC;
         ++iters;
         {
           OV t;
@@ -624,12 +704,19 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
 #pragma unroll
             for (int r = 0; r < R0; ++r) y.v[s][r] = cadd(t.v[s][r], cmul_is(y.v[s][r], al));
         }
-        E::block_dots(basis, y, j + 1, c, c.hcol);
+        // classical Gram-Schmidt; a second pass when the first cancelled most of w
+        // (||w'||^2 < ||w||^2 / 2, "twice is enough")
+        E::block_dots(basis, y, j + 1, c, c.hcol, true);
+        const double w2 = uniform_d(c.hcol[j + 1].x);
         E::block_axpy(basis, c.hcol, j + 1, y);
-        E::block_dots(basis, y, j + 1, c, c.y);
-        E::block_axpy(basis, c.y, j + 1, y);
-        for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);
-        const double hn = sqrt(E::block_sum1(E::norm2(y), c));  // its barriers order the hcol update
+        double hn2 = E::block_sum1(E::norm2(y), c);
+        if (hn2 < 0.5 * w2) {
+          E::block_dots(basis, y, j + 1, c, c.y);
+          E::block_axpy(basis, c.y, j + 1, y);
+          for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);
+          hn2 = E::block_sum1(E::norm2(y), c);  // its barriers order the hcol update
+        }
+        const double hn = sqrt(hn2);
         E::givens_update(j, hn, c);
         const double gabs = uniform_d(c.scal[0]);
         if (!isfinite(hn) || !isfinite(gabs)) {
@@ -641,7 +728,7 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
 #pragma unroll
           for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int r = 0; r < R0; ++r) y.v[s][r] = make_double2(y.v[s][r].x / hn, y.v[s][r].y / hn);
+            for (int r = 0; r < R0; ++r) y.v[s][r] = mk(y.v[s][r].x / hn, y.v[s][r].y / hn);
           ++j;
           E::store(y, basis + (size_t)j * E::VEC);
           request(basis + (size_t)j * E::VEC, true);
@@ -655,8 +742,8 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
           E::load(x, xg);
 #pragma unroll 1
           for (int i = 0; i < k; ++i) {
-            const double2* Vi = basis + (size_t)i * E::VEC;
-            const double2 yi = c.y[i];
+            const cplx* Vi = basis + (size_t)i * E::VEC;
+            const cplx yi = c.y[i];
 #pragma unroll
             for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -737,15 +824,16 @@ template <int N>
 __global__ void __launch_bounds__(Eng<N>::T) k_apply_h(KArgs a) {
   using E = Eng<N>;
   if ((int)blockIdx.x >= a.nlist) return;
-  extern __shared__ double2 smem[];
+  extern __shared__ double2 smem_raw[];
+  GQD_L cplx* smem = (GQD_L cplx*)smem_raw;
   const ItemMeta im = a.items[a.list[blockIdx.x]];
   const auto c = E::make_ctx(smem, 0, a, im);
   typename E::OV y;
-  E::apply_A(a.psi + im.off, y, c);
-  E::store(y, a.aux + im.off);
-  E::apply_A(a.aux + im.off, y, c);
-  E::finish_H(y, a.psi + im.off, c);
-  E::store(y, a.aux + im.off);
+  E::apply_A((cplx*)a.psi + im.off, y, c);
+  E::store(y, (cplx*)a.aux + im.off);
+  E::apply_A((cplx*)a.aux + im.off, y, c);
+  E::finish_H(y, (cplx*)a.psi + im.off, c);
+  E::store(y, (cplx*)a.aux + im.off);
 }
 
 // out[item] = (norm, energy, P1, P2); energy = ||A psi||^2 / (2m) + <psi|V psi>
@@ -753,11 +841,12 @@ template <int N>
 __global__ void __launch_bounds__(Eng<N>::T) k_diag(KArgs a) {
   using E = Eng<N>;
   if ((int)blockIdx.x >= a.nlist) return;
-  extern __shared__ double2 smem[];
+  extern __shared__ double2 smem_raw[];
+  GQD_L cplx* smem = (GQD_L cplx*)smem_raw;
   const int item = a.list[blockIdx.x];
   const ItemMeta im = a.items[item];
   const auto c = E::make_ctx(smem, 0, a, im);
-  const double2* x = a.psi + im.off;
+  const cplx* x = (cplx*)a.psi + im.off;
   double p0 = 0.0, p1 = 0.0, pv = 0.0;
 #pragma unroll
   for (int r = 0; r < E::R0; ++r) {
@@ -787,18 +876,19 @@ template <int N>
 __global__ void __launch_bounds__(Eng<N>::T) k_inner(KArgs a) {
   using E = Eng<N>;
   if ((int)blockIdx.x >= a.nlist) return;
-  extern __shared__ double2 smem[];
+  extern __shared__ double2 smem_raw[];
+  GQD_L cplx* smem = (GQD_L cplx*)smem_raw;
   const int item = a.list[blockIdx.x];
   const ItemMeta im = a.items[item];
   const auto c = E::make_ctx(smem, 0, a, im);
-  const double2* x = a.psi + im.off;
-  const double2* y = a.aux + im.off;
+  const cplx* x = (cplx*)a.psi + im.off;
+  const cplx* y = (cplx*)a.aux + im.off;
   double re = 0.0, imv = 0.0;
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int r = 0; r < E::R0; ++r) {
-      const double2 z = cconjmul(x[s * N + E::pt(r)], y[s * N + E::pt(r)]);
+      const cplx z = cconjmul(x[s * N + E::pt(r)], y[s * N + E::pt(r)]);
       re += z.x;
       imv += z.y;
     }
