@@ -51,6 +51,7 @@ struct gqd_handle {
   ItemMeta* d_items = nullptr;
   int* d_lists[kNumClasses] = {};
   double2* d_tw = nullptr;
+  long long tw_off[kNumClasses] = {};
   ItemStats* d_stats = nullptr;
   std::vector<ItemStats> h_stats;
   const double* V = nullptr;
@@ -105,6 +106,7 @@ gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
       if (h->class_lists[c].empty()) continue;
       a.list = h->d_lists[c];
       a.nlist = (int)h->class_lists[c].size();
+      a.tw = h->d_tw + h->tw_off[c];
       GQD_HIP(fn(c, a, stream));
     }
     return GQD_OK;
@@ -117,6 +119,7 @@ gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
     GQD_HIP(hipStreamWaitEvent(h->side[c], h->ev_fork, 0));
     a.list = h->d_lists[c];
     a.nlist = (int)h->class_lists[c].size();
+    a.tw = h->d_tw + h->tw_off[c];
     GQD_HIP(fn(c, a, h->side[c]));
     GQD_HIP(hipEventRecord(h->ev_join[c], h->side[c]));
     GQD_HIP(hipStreamWaitEvent(stream, h->ev_join[c], 0));
@@ -130,7 +133,6 @@ KArgs base_args(const gqd_handle* h) {
   a.items = h->d_items;
   a.V = h->V;
   a.F = h->F;
-  a.tw = h->d_tw;
   a.inv2m = 1.0 / (2.0 * h->mass);
   a.mass = h->mass;
   a.stats = h->d_stats;
@@ -259,15 +261,29 @@ gqd_status gqd_create(gqd_handle** out, const gqd_grid_desc* g) {
     if ((e = hipMemcpy(h->d_lists[c], h->class_lists[c].data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup(hip_fail(e, "hipMemcpy lists"));
   }
-  // twiddles exp(-2 pi i k / 4096), evaluated in extended precision and rounded once
-  std::vector<double2> tw(kTwiddleN);
+  // per-pass twiddle tables of every size class, evaluated in extended precision and
+  // rounded once: entry k (R - 1) + r - 1 of a pass = exp(-2 pi i r k / (Ns R))
+  std::vector<double2> tw;
   const long double pi = 3.141592653589793238462643383279502884L;
-  for (int k = 0; k < kTwiddleN; ++k) {
-    const long double ang = 2.0L * pi * (long double)k / (long double)kTwiddleN;
-    tw[k] = make_double2((double)cosl(ang), (double)-sinl(ang));
+  for (int c = 0; c < kNumClasses; ++c) {
+    h->tw_off[c] = (long long)tw.size();
+    PassNR ps[6] = {};
+    const int np = twiddle_passes(c, ps);
+    for (int p = 0; p < np; ++p) {
+      const long double L = (long double)ps[p].Ns * ps[p].R;
+      for (int k = 0; k < ps[p].Ns; ++k)
+        for (int r = 1; r < ps[p].R; ++r) {
+          const long double ang = 2.0L * pi * (long double)(r * k) / L;
+          tw.push_back(make_double2((double)cosl(ang), (double)-sinl(ang)));
+        }
+    }
+    if ((long long)tw.size() - h->tw_off[c] != class_table_size(c)) {
+      gqd_destroy(h);
+      return fail(GQD_ERR_INVALID, "internal: twiddle table size mismatch");
+    }
   }
-  if ((e = hipMalloc(&h->d_tw, sizeof(double2) * kTwiddleN)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc twiddles"));
-  if ((e = hipMemcpy(h->d_tw, tw.data(), sizeof(double2) * kTwiddleN, hipMemcpyHostToDevice)) != hipSuccess)
+  if ((e = hipMalloc(&h->d_tw, sizeof(double2) * tw.size())) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc twiddles"));
+  if ((e = hipMemcpy(h->d_tw, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMemcpy twiddles"));
   if ((e = hipMalloc(&h->d_stats, sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc stats"));
   if ((e = hipMemset(h->d_stats, 0, sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMemset stats"));

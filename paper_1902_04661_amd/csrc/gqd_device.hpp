@@ -9,6 +9,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "gqd_internal.h"
+
 namespace gqd {
 
 // Address-space qualified pointers: global memory (1) and LDS (3).  Generic pointers
@@ -146,61 +148,12 @@ __device__ __forceinline__ int lane_tid() {
 }
 
 // ------------------------------------------------------------------------ FFT plans
-// Stockham passes of radices (R0, R1, R2[, R3]) with product N and T = N / R0 threads.
-// Every pass has 2N/R butterflies (two surfaces), a whole multiple of T, and T is a
-// whole number of 64-lane waves.  R3 = 1 means a three-pass plan.
-template <int N> struct Plan;
-template <> struct Plan<256>  { static constexpr int R0 = 4, R1 = 8, R2 = 8, R3 = 1; };
-template <> struct Plan<512>  { static constexpr int R0 = 4, R1 = 8, R2 = 4, R3 = 4; };
-template <> struct Plan<1024> { static constexpr int R0 = 4, R1 = 8, R2 = 8, R3 = 4; };
-template <> struct Plan<2048> { static constexpr int R0 = 4, R1 = 8, R2 = 8, R3 = 8; };
-template <> struct Plan<4096> { static constexpr int R0 = 8, R1 = 8, R2 = 8, R3 = 8; };
-
-constexpr int TW_N = 4096;  // twiddle table: exp(-2 pi i k / 4096), k < 4096
-
-// Twiddle exp(S * 2 pi i * num / den) for den | TW_N, from the table.
-template <int S>
-__device__ __forceinline__ cplx tw_lookup(const GQD_G cplx* __restrict__ tw, int idx4096) {
-  cplx w = tw[idx4096];
-  return S < 0 ? w : mk(w.x, -w.y);
-}
-
-// One in-place Stockham pass over 2 sequences of length N in LDS (seq s at lds[s*N]).
-// Butterfly j (< N/R) of sequence s reads x[j + r N/R], twiddles by w_{Ns R}^{r k}
-// (k = j mod Ns), applies the radix-R DFT and writes y[(j/Ns) Ns R + k + r Ns].
-template <int N, int T, int R, int Ns, int S>
-__device__ __forceinline__ void stockham_lds(GQD_L cplx* lds, const GQD_G cplx* __restrict__ tw) {
-  constexpr int NB = 2 * N / R;
-  static_assert(NB % T == 0, "butterflies must be a multiple of the thread count");
-  constexpr int PER = NB / T;
-  cplx x[PER][R];
-  int tid = lane_tid();
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int b = tid + q * T;
-    const int s = b / (N / R), j = b % (N / R);
-#pragma unroll
-    for (int r = 0; r < R; ++r) x[q][r] = lds[s * N + j + r * (N / R)];
-  }
-  __syncthreads();
-  tid = lane_tid();
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int b = tid + q * T;
-    const int s = b / (N / R), j = b % (N / R);
-    const int k = j % Ns;
-    if constexpr (Ns > 1) {
-      constexpr int step = TW_N / (Ns * R);
-#pragma unroll
-      for (int r = 1; r < R; ++r) x[q][r] = cmul(x[q][r], tw_lookup<S>(tw, r * k * step));
-    }
-    DFT<R, S>::run(x[q]);
-    const int base = (j / Ns) * Ns * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) lds[s * N + base + r * Ns] = x[q][r];
-  }
-  __syncthreads();
-}
+template <int N> struct ClassOf;
+template <> struct ClassOf<256>  { static constexpr int v = 0; };
+template <> struct ClassOf<512>  { static constexpr int v = 1; };
+template <> struct ClassOf<1024> { static constexpr int v = 2; };
+template <> struct ClassOf<2048> { static constexpr int v = 3; };
+template <> struct ClassOf<4096> { static constexpr int v = 4; };
 
 // -------------------------------------------------------------------- reductions
 template <int T>

@@ -5,7 +5,6 @@
 
 namespace gqd {
 
-constexpr int kTwiddleN = 4096;  // twiddle table exp(-2 pi i k / 4096)
 constexpr int kMaxLevels = 4;  // compositions up to order 10
 constexpr int kMaxArity = 5;   // Suzuki fractal has 5 substeps per level
 constexpr int kMaxRestart = 64;
@@ -68,7 +67,7 @@ struct KArgs {
   double* gF;           // adjoint: dL/dF12 accumulation [n] per item (foff layout)
   double* out;          // diagnostics output
   double2* work;        // workspace base, (m + kWorkExtra) vectors of 2n per item
-  const double2* tw;    // exp(-2 pi i k / 4096)
+  const double2* tw;    // per-pass twiddle tables of this launch's size class
   double inv2m;         // 1 / (2 mass)
   double mass;
   SolveCfg sc;
@@ -83,16 +82,66 @@ struct KArgs {
   ItemStats* stats;
 };
 
-// Sizes up to this one keep the input / partial result of an H application in LDS.
-constexpr int kParkMaxN = 2048;
+// Sizes up to this one use two LDS transform buffers (one barrier per pass).
+constexpr int kPingPongMaxN = 2048;
+
+// Stockham plans per size class: radices (R0, R1, R2, R3); R3 = 1 means three passes.
+// T = N / R0 threads per item; every pass has 2N/R butterflies, a multiple of T.
+constexpr int kPlan[kNumClasses][4] = {
+    {4, 8, 8, 1},  // 256
+    {4, 8, 4, 4},  // 512
+    {4, 8, 8, 4},  // 1024
+    {4, 8, 8, 8},  // 2048
+    {8, 8, 8, 8},  // 4096
+};
+
+// Twiddled passes of one application of p, in execution order (the first forward pass
+// has Ns = 1 and needs none): (Ns, R) of each.  Both the host table builder and the
+// kernels enumerate them with this function.
+struct PassNR {
+  int Ns, R;
+};
+constexpr int twiddle_passes(int cls, PassNR* out) {
+  const int R0 = kPlan[cls][0], R1 = kPlan[cls][1], R2 = kPlan[cls][2], R3 = kPlan[cls][3];
+  int n = 0;
+  if (R3 == 1) {
+    out[n++] = PassNR{R0, R1};            // forward
+    out[n++] = PassNR{R0 * R1, R2};       // forward, fused with the first inverse pass
+    out[n++] = PassNR{R2, R1};            // inverse
+    out[n++] = PassNR{R2 * R1, R0};       // inverse, to owned points
+  } else {
+    out[n++] = PassNR{R0, R1};
+    out[n++] = PassNR{R0 * R1, R2};
+    out[n++] = PassNR{R0 * R1 * R2, R3};  // fused
+    out[n++] = PassNR{R3, R2};
+    out[n++] = PassNR{R3 * R2, R1};
+    out[n++] = PassNR{R3 * R2 * R1, R0};
+  }
+  return n;
+}
+// Per-pass twiddle table: entry k (R - 1) + r - 1 = exp(-2 pi i r k / (Ns R)), k < Ns.
+constexpr int pass_table_size(PassNR p) { return p.Ns * (p.R - 1); }
+constexpr int class_table_size(int cls) {
+  PassNR ps[6] = {};
+  const int n = twiddle_passes(cls, ps);
+  int t = 0;
+  for (int i = 0; i < n; ++i) t += pass_table_size(ps[i]);
+  return t;
+}
+constexpr int pass_table_offset(int cls, int pass) {
+  PassNR ps[6] = {};
+  twiddle_passes(cls, ps);
+  int t = 0;
+  for (int i = 0; i < pass; ++i) t += pass_table_size(ps[i]);
+  return t;
+}
 
 // LDS bytes needed by a launch at size N with restart length m.
 inline size_t lds_bytes(int N, int m) {
   const int T = (N == 4096) ? 512 : (N / 4);  // threads per item (N / R0 of the plan)
   const int W = T / 64;
-  const size_t park = (N <= kParkMaxN) ? 2 * (size_t)N : 0;
-  const size_t c = 2 * (size_t)N + park + (size_t)W * (m + 1) + 2 * (m + 1) + 2 * (size_t)m +
-                   (size_t)m * (m + 1) / 2;
+  const size_t fft = (N <= kPingPongMaxN) ? 4 * (size_t)N : 2 * (size_t)N;
+  const size_t c = fft + (size_t)W * (m + 1) + 2 * (m + 1) + 2 * (size_t)m + (size_t)m * (m + 1) / 2;
   return c * 16 + (size_t)m * 8 + 16 * 8;
 }
 

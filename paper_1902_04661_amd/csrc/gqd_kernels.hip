@@ -9,18 +9,19 @@
 
 namespace gqd {
 
-static_assert(TW_N == kTwiddleN, "twiddle table size");
 
 template <int N>
 struct Eng {
-  using P = Plan<N>;
-  static constexpr int R0 = P::R0, R1 = P::R1, R2 = P::R2, R3 = P::R3;
+  static constexpr int CLS = ClassOf<N>::v;
+  static constexpr int R0 = kPlan[CLS][0], R1 = kPlan[CLS][1], R2 = kPlan[CLS][2], R3 = kPlan[CLS][3];
   static constexpr int T = N / R0;
   static constexpr int W = T / 64;
   static_assert(T % 64 == 0, "whole waves only");
   static constexpr int RF = (R3 == 1) ? R2 : R3;  // radix of the fused k-space pass
   static constexpr size_t VEC = 2 * (size_t)N;    // complex elements of one state vector
-  static constexpr bool kPark = N <= kParkMaxN;     // H-application scratch in LDS
+  // N <= kPingPongMaxN: two LDS transform buffers (one barrier per pass) and a
+  // quarter-period twiddle table in LDS; larger N: one buffer, table in global memory
+  static constexpr bool kPP = N <= kPingPongMaxN;
 
   struct OV {
     cplx v[2][R0];
@@ -28,8 +29,7 @@ struct Eng {
 
   using LP = GQD_L cplx*;
   struct Ctx {
-    GQD_L cplx* fft;   // [2N]
-    GQD_L cplx* park;  // [2N] LDS scratch at owned points when kPark, else null
+    GQD_L cplx* fft;   // [2N] (in-place) or [4N] (two buffers)
     GQD_L cplx* part;  // [W][kmax]
     GQD_L cplx* hcol;  // [kmax]
     GQD_L cplx* g;     // [kmax]
@@ -54,8 +54,7 @@ struct Eng {
     const int kmax = m + 1;
     c.kmax = kmax;
     c.fft = smem;
-    c.park = kPark ? c.fft + 2 * N : nullptr;
-    c.part = c.fft + (kPark ? 4 : 2) * N;
+    c.part = c.fft + (kPP ? 4 : 2) * N;
     c.hcol = c.part + W * kmax;
     c.g = c.hcol + kmax;
     c.sn = c.g + kmax;
@@ -160,10 +159,58 @@ struct Eng {
   }
 
   // --------------------------------------------------------------- Fourier passes
+  // Twiddles come from per-pass tables (built by the host): butterfly k of a pass with
+  // stride Ns and radix R finds exp(-2 pi i r k / (Ns R)), r = 1..R-1, contiguously at
+  // tw + offset + k (R - 1).  Inverse passes multiply by the conjugate.
+  template <int S>
+  static __device__ __forceinline__ cplx twmul(cplx x, cplx w) {
+    return S < 0 ? cmul(x, w) : mk(x.x * w.x + x.y * w.y, x.y * w.x - x.x * w.y);
+  }
+
+  // One Stockham pass over both surfaces, src -> dst (dst == src when in place).
+  // Butterfly j (< N/R) of surface s reads x[j + r N/R], twiddles by w_{Ns R}^{r k}
+  // (k = j mod Ns), applies the radix-R DFT and writes y[(j/Ns) Ns R + k + r Ns].
+  template <int R, int Ns, int S, int P>
+  static __device__ __forceinline__ void pass(const GQD_L cplx* src, GQD_L cplx* dst, const GQD_G cplx* tw) {
+    static_assert(pass_table_size(PassNR{Ns, R}) > 0, "twiddled pass");
+    constexpr int OFF = pass_table_offset(CLS, P);
+    constexpr int NB = 2 * N / R;
+    static_assert(NB % T == 0, "butterflies must be a multiple of the thread count");
+    constexpr int PER = NB / T;
+    cplx x[PER][R];
+    int tid = lane_tid();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int b = tid + q * T;
+      const int s = b / (N / R), j = b % (N / R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[q][r] = src[s * N + j + r * (N / R)];
+    }
+    if constexpr (!kPP) __syncthreads();  // in place: all reads before any write
+    tid = lane_tid();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int b = tid + q * T;
+      const int s = b / (N / R), j = b % (N / R);
+      const int k = j % Ns;
+      const GQD_G cplx* tk = tw + OFF + k * (R - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) x[q][r] = twmul<S>(x[q][r], tk[r - 1]);
+      DFT<R, S>::run(x[q]);
+      const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[s * N + base + r * Ns] = x[q][r];
+    }
+    __syncthreads();
+  }
+
   // Fused last forward pass (radix RF, Ns = N/RF), momentum multiply and first
   // inverse pass (radix RF, Ns = 1): butterfly j's forward outputs are the k-space
   // points j + r N/RF, exactly the inputs of the inverse butterfly j.
-  static __device__ __forceinline__ void fused_kspace(const Ctx& c, const GQD_G cplx* tw) {
+  template <int P>
+  static __device__ __forceinline__ void fused_kspace(const GQD_L cplx* src, GQD_L cplx* dst,
+                                                      const GQD_G cplx* tw, const Ctx& c) {
+    constexpr int OFF = pass_table_offset(CLS, P);
     constexpr int NB = 2 * N / RF;
     static_assert(NB % T == 0, "fused pass butterflies");
     constexpr int PER = NB / T;
@@ -175,18 +222,18 @@ struct Eng {
       const int b = tid + q * T;
       const int s = b / Ns, j = b % Ns;
 #pragma unroll
-      for (int r = 0; r < RF; ++r) x[q][r] = c.fft[s * N + j + r * Ns];
+      for (int r = 0; r < RF; ++r) x[q][r] = src[s * N + j + r * Ns];
     }
-    __syncthreads();
+    if constexpr (!kPP) __syncthreads();
     const double scale = opaque_d(c.pscale) / (double)N;
     tid = lane_tid();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int b = tid + q * T;
       const int s = b / Ns, j = b % Ns;
-      constexpr int step = TW_N / N;
+      const GQD_G cplx* tk = tw + OFF + j * (RF - 1);
 #pragma unroll
-      for (int r = 1; r < RF; ++r) x[q][r] = cmul(x[q][r], tw_lookup<-1>(tw, r * j * step));
+      for (int r = 1; r < RF; ++r) x[q][r] = cmul(x[q][r], tk[r - 1]);
       DFT<RF, -1>::run(x[q]);
 #pragma unroll
       for (int r = 0; r < RF; ++r) {
@@ -196,14 +243,15 @@ struct Eng {
       }
       DFT<RF, +1>::run(x[q]);
 #pragma unroll
-      for (int r = 0; r < RF; ++r) c.fft[s * N + j * RF + r] = x[q][r];
+      for (int r = 0; r < RF; ++r) dst[s * N + j * RF + r] = x[q][r];
     }
     __syncthreads();
   }
 
   // u = p x on both surfaces (forward DFT, multiply by p_k, inverse DFT / N).
   static __device__ void kinetic(const OV& x, OV& u, const Ctx& c) {
-    const GQD_G cplx* tw = opaque(c.tw);
+    GQD_L cplx* b0 = c.fft;
+    GQD_L cplx* b1 = kPP ? c.fft + 2 * N : c.fft;
     // pass A: radix R0, Ns = 1, from owned registers (butterfly j = thread)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -212,35 +260,37 @@ struct Eng {
       for (int r = 0; r < R0; ++r) y[r] = x.v[s][r];
       DFT<R0, -1>::run(y);
 #pragma unroll
-      for (int r = 0; r < R0; ++r) c.fft[s * N + lane_tid() * R0 + r] = y[r];
+      for (int r = 0; r < R0; ++r) b0[s * N + lane_tid() * R0 + r] = y[r];
     }
     __syncthreads();
+    constexpr int PL = (R3 == 1) ? 3 : 5;  // table index of the last pass
     if constexpr (R3 == 1) {
-      stockham_lds<N, T, R1, R0, -1>(c.fft, opaque(tw));
-      fused_kspace(c, opaque(tw));
-      stockham_lds<N, T, R1, R2, +1>(c.fft, opaque(tw));
+      pass<R1, R0, -1, 0>(b0, b1, opaque(c.tw));
+      fused_kspace<1>(b1, b0, opaque(c.tw), c);
+      pass<R1, R2, +1, 2>(b0, b1, opaque(c.tw));
     } else {
-      stockham_lds<N, T, R1, R0, -1>(c.fft, opaque(tw));
-      stockham_lds<N, T, R2, R0 * R1, -1>(c.fft, opaque(tw));
-      fused_kspace(c, opaque(tw));
-      stockham_lds<N, T, R2, R3, +1>(c.fft, opaque(tw));
-      stockham_lds<N, T, R1, R3 * R2, +1>(c.fft, opaque(tw));
+      pass<R1, R0, -1, 0>(b0, b1, opaque(c.tw));
+      pass<R2, R0 * R1, -1, 1>(b1, b0, opaque(c.tw));
+      fused_kspace<2>(b0, b1, opaque(c.tw), c);
+      pass<R2, R3, +1, 3>(b1, b0, opaque(c.tw));
+      pass<R1, R3 * R2, +1, 4>(b0, b1, opaque(c.tw));
     }
-    tw = opaque(tw);
+    const GQD_G cplx* tl = opaque(c.tw) + pass_table_offset(CLS, PL) + lane_tid() * (R0 - 1);
     // last inverse pass: radix R0, Ns = T, butterfly j = thread -> owned points
-    constexpr int step = TW_N / N;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       cplx y[R0];
 #pragma unroll
-      for (int r = 0; r < R0; ++r) y[r] = c.fft[s * N + pt(r)];
+      for (int r = 0; r < R0; ++r) y[r] = b1[s * N + pt(r)];
 #pragma unroll
-      for (int r = 1; r < R0; ++r) y[r] = cmul(y[r], tw_lookup<+1>(tw, r * lane_tid() * step));
+      for (int r = 1; r < R0; ++r) y[r] = twmul<+1>(y[r], tl[r - 1]);
       DFT<R0, +1>::run(y);
 #pragma unroll
       for (int r = 0; r < R0; ++r) u.v[s][r] = y[r];
     }
-    __syncthreads();  // the LDS buffer is free again
+    // in place, the buffer is reused by the next pass A; with two buffers the next
+    // writer of b1 comes after a barrier
+    if constexpr (!kPP) __syncthreads();
   }
 
   // y = [p - i F] x for x at xg (F12 couples surface 2 into surface 1, F21 = -F12).
@@ -274,15 +324,7 @@ struct Eng {
         y.v[s][r] = cadd(cscale(y.v[s][r], c.inv2m), cscale(xq[s * N + pt(r)], V[s * N + pt(r)]));
   }
 
-  // Owned points of an LDS buffer (each lane only touches its own points).
-  static __device__ __forceinline__ void lds_store(const OV& x, GQD_L cplx* l) {
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int r = 0; r < R0; ++r) l[s * N + pt(r)] = x.v[s][r];
-  }
-
-  // y += -i F x on owned points (x at xs: LDS park or a global vector)
+  // y += -i F x on owned points (x read from a global vector)
   template <class P>
   static __device__ __forceinline__ void couple(OV& y, P xs, const Ctx& c) {
     const GQD_G double* F = opaque(c.F);
@@ -295,7 +337,7 @@ struct Eng {
     }
   }
 
-  // pre = (-i F chi) / (2m) + V x written to dst (LDS park or global), x read from xs;
+  // pre = (-i F chi) / (2m) + V x written to dst (global), x read from xs;
   // the outer A's coupling and the potential, formed before the second transform.
   template <class P, class Q>
   static __device__ __forceinline__ void make_pre(const OV& chi, P xs, Q dst, const Ctx& c) {
@@ -311,6 +353,36 @@ struct Eng {
       dst[pt(r)] = p0;
       dst[N + pt(r)] = p1;
     }
+  }
+
+  // register forms: x (then pre) held at owned points
+  static __device__ __forceinline__ void couple(OV& y, const OV& x, const Ctx& c) {
+    const GQD_G double* F = opaque(c.F);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const double f = F[pt(r)];
+      y.v[0][r] = cadd(y.v[0][r], cmul_is(x.v[1][r], -f));
+      y.v[1][r] = cadd(y.v[1][r], cmul_is(x.v[0][r], f));
+    }
+  }
+  static __device__ __forceinline__ void make_pre(const OV& chi, OV& xp, const Ctx& c) {
+    const GQD_G double* F = opaque(c.F);
+    const GQD_G double* V = opaque(c.V);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const double f = F[pt(r)];
+      const double v0 = V[pt(r)], v1 = V[N + pt(r)];
+      const cplx p0 = cadd(cscale(cmul_is(chi.v[1][r], -f), c.inv2m), cscale(xp.v[0][r], v0));
+      const cplx p1 = cadd(cscale(cmul_is(chi.v[0][r], f), c.inv2m), cscale(xp.v[1][r], v1));
+      xp.v[0][r] = p0;
+      xp.v[1][r] = p1;
+    }
+  }
+  static __device__ __forceinline__ void add_pre(OV& y, const OV& pre, const Ctx& c) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) y.v[s][r] = cadd(cscale(y.v[s][r], c.inv2m), pre.v[s][r]);
   }
 
   // y <- y / (2m) + pre
@@ -423,7 +495,7 @@ enum Pc {
 //
 // The kernel is a small machine around a single operator application so that the
 // Fourier-transform code exists once: each loop turn applies A = p - iF to a global
-// vector (H takes two turns, the inner A x parked in the CHI slot), then the current
+// vector (H takes two turns, the inner A x kept in registers between them), then the current
 // program counter consumes the result and requests the next application.
 //
 // Propagation, per substep of length h = tau_c dt, alpha = h/2 (Sec. II.C-D):
@@ -484,7 +556,7 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
   int j = 0, iters = 0, after = kSubstep;
 
   int pc = kSubstep;
-  OV y;
+  OV y, keep;
 
   auto request = [&](const cplx* src, bool h) {
     pending = true;
@@ -532,20 +604,20 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
     if (bad) break;
     if (pending) {
       // one transform per turn: turn 1 takes the input from opsrc, turn 2 (H only) takes
-      // chi = A x from registers; x and the partial result live in the park buffer
-      // (LDS, N <= 2048) or in the CHI slot (global, larger N)
+      // chi = A x from registers; x and then the partial result are kept in registers
+      // (two-buffer mode) or read from opsrc / parked in the CHI slot (larger N)
       OV t;
       if (half == 0) {
         E::load(t, opsrc);
-        if constexpr (E::kPark) E::lds_store(t, c.park);
+        if constexpr (E::kPP) keep = t;
       } else {
         t = y;
       }
       E::kinetic(t, y, c);
       if (half == 0) {
-        if constexpr (E::kPark) {
-          E::couple(y, c.park, c);
-          if (opH) E::make_pre(y, c.park, c.park, c);
+        if constexpr (E::kPP) {
+          E::couple(y, keep, c);
+          if (opH) E::make_pre(y, keep, c);
         } else {
           E::couple(y, opaque(opsrc), c);
           if (opH) E::make_pre(y, opaque(opsrc), opaque(CHI), c);
@@ -555,8 +627,8 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
           continue;
         }
       } else {
-        if constexpr (E::kPark) {
-          E::add_pre(y, c.park, c);
+        if constexpr (E::kPP) {
+          E::add_pre(y, keep, c);
         } else {
           E::add_pre(y, opaque(CHI), c);
         }
