@@ -82,6 +82,8 @@ def main(argv=None):
     ap.add_argument("--single-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device once (HBM counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs each batch on a single MI355X "
@@ -94,6 +96,14 @@ def main(argv=None):
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8}), flush=True)
+        return 0
     opts = gqd.SolverOpts(tol=TOL, restart=32)
 
     # ---------------------------------------------------------------- batched run

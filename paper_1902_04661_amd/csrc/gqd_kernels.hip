@@ -117,22 +117,33 @@ struct Eng {
       const double nn = wave_sum(norm2(w));
       if (lane == 0) c.part[wv * c.kmax + K] = mk(nn, 0.0);
     }
+    // two basis vectors per turn so that their loads and reductions overlap
 #pragma unroll 1
-    for (int i = 0; i < K; ++i) {
-      const GQD_G cplx* Vi = opaque(basis + (size_t)i * VEC);
-      double ax = 0.0, ay = 0.0;
+    for (int i = 0; i < K; i += 2) {
+      const bool two = i + 1 < K;
+      const GQD_G cplx* Va = opaque(basis + (size_t)i * VEC);
+      const GQD_G cplx* Vb = opaque(basis + (size_t)(two ? i + 1 : i) * VEC);
+      double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-          const cplx b = Vi[s * N + pt(r)];
+          const cplx va = Va[s * N + pt(r)];
+          const cplx vb = Vb[s * N + pt(r)];
           const cplx z = w.v[s][r];
-          ax += b.x * z.x + b.y * z.y;
-          ay += b.x * z.y - b.y * z.x;
+          ax += va.x * z.x + va.y * z.y;
+          ay += va.x * z.y - va.y * z.x;
+          bx += vb.x * z.x + vb.y * z.y;
+          by += vb.x * z.y - vb.y * z.x;
         }
       ax = wave_sum(ax);
       ay = wave_sum(ay);
-      if (lane == 0) c.part[wv * c.kmax + i] = mk(ax, ay);
+      bx = wave_sum(bx);
+      by = wave_sum(by);
+      if (lane == 0) {
+        c.part[wv * c.kmax + i] = mk(ax, ay);
+        if (two) c.part[wv * c.kmax + i + 1] = mk(bx, by);
+      }
     }
     __syncthreads();
     const int Kt = with_norm ? K + 1 : K;
@@ -148,13 +159,20 @@ struct Eng {
   // w -= sum_i h[i] V_i, i < K (h in LDS)
   static __device__ void block_axpy(const cplx* __restrict__ basis, const GQD_L cplx* h, int K, OV& w) {
 #pragma unroll 1
-    for (int i = 0; i < K; ++i) {
-      const GQD_G cplx* Vi = opaque(basis + (size_t)i * VEC);
-      const cplx hi = h[i];
+    for (int i = 0; i < K; i += 2) {
+      const bool two = i + 1 < K;
+      const GQD_G cplx* Va = opaque(basis + (size_t)i * VEC);
+      const GQD_G cplx* Vb = opaque(basis + (size_t)(two ? i + 1 : i) * VEC);
+      const cplx ha = h[i];
+      const cplx hb = two ? h[i + 1] : mk(0.0, 0.0);
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int r = 0; r < R0; ++r) w.v[s][r] = csub(w.v[s][r], cmul(hi, Vi[s * N + pt(r)]));
+        for (int r = 0; r < R0; ++r) {
+          const cplx va = Va[s * N + pt(r)];
+          const cplx vb = Vb[s * N + pt(r)];
+          w.v[s][r] = csub(csub(w.v[s][r], cmul(ha, va)), cmul(hb, vb));
+        }
     }
   }
 
@@ -501,9 +519,10 @@ enum Pc {
 // Propagation, per substep of length h = tau_c dt, alpha = h/2 (Sec. II.C-D):
 //   midpoint (Eq. 19):  x = (1 + i alpha H)^-1 psi;  psi' = (1 - i alpha H) x, or 2x - psi
 //   trapezoid (Eq. 18): b = (1 - i alpha H) psi;     psi' = (1 + i alpha H)^-1 b
-// Each inverse is restarted GMRES(m) from x0 = (1 - i alpha H) b with classical
-// Gram-Schmidt applied twice and Givens rotations; it stops when the residual
-// estimate is <= tol ||b||.
+// Each inverse is restarted GMRES(m) from x0 = (1 - i alpha H) b, with the Arnoldi
+// basis built from H (classical Gram-Schmidt, a second pass on cancellation) and
+// Givens rotations on the Hessenberg matrix of 1 + i alpha H; it stops when the
+// residual estimate is <= tol ||b||.
 //
 // Reverse sweep, substeps in reverse order: phi = (1 - i alpha H)^-1 psi,
 // mu = (1 - i alpha H)^-1 lambda, psi <- 2 phi - psi, lambda <- 2 mu - lambda,
@@ -766,18 +785,12 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
         break;
       }
       case kSolveArnoldi: {
-        const cplx* Vj = basis + (size_t)j * E::VEC;
+        // Arnoldi on H (the Krylov space of 1 + i al H is that of H): y = H v_j is
+        // orthogonalised against v_0..v_j by classical Gram-Schmidt, with a second pass
+        // only when the first cancels more than half of |w|^2 ("twice is enough").
+        // Column j of the Hessenberg matrix of X = 1 + i al H is delta_ij + i al h_ij,
+        // and v_(j+1) = i sign(al) w'/|w'| makes its subdiagonal |al| |w'| real.
         ++iters;
-        {
-          OV t;
-          E::load(t, Vj);
-#pragma unroll
-          for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int r = 0; r < R0; ++r) y.v[s][r] = cadd(t.v[s][r], cmul_is(y.v[s][r], al));
-        }
-        // classical Gram-Schmidt; a second pass when the first cancelled most of w
-        // (||w'||^2 < ||w||^2 / 2, "twice is enough")
         E::block_dots(basis, y, j + 1, c, c.hcol, true);
         const double w2 = uniform_d(c.hcol[j + 1].x);
         E::block_axpy(basis, c.hcol, j + 1, y);
@@ -789,7 +802,12 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
           hn2 = E::block_sum1(E::norm2(y), c);  // its barriers order the hcol update
         }
         const double hn = sqrt(hn2);
-        E::givens_update(j, hn, c);
+        for (int i = threadIdx.x; i <= j; i += T) {
+          const cplx hx = cmul_is(c.hcol[i], al);  // i al h_ij
+          c.hcol[i] = (i == j) ? mk(1.0 + hx.x, hx.y) : hx;
+        }
+        __syncthreads();
+        E::givens_update(j, fabs(al) * hn, c);
         const double gabs = uniform_d(c.scal[0]);
         if (!isfinite(hn) || !isfinite(gabs)) {
           bad = true;
@@ -797,10 +815,11 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
         }
         const bool cv = gabs <= tolb;
         if (!cv && hn != 0.0 && iters < a.sc.maxit && j + 1 < m) {
+          const double sc = (al >= 0.0 ? 1.0 : -1.0) / hn;
 #pragma unroll
           for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int r = 0; r < R0; ++r) y.v[s][r] = mk(y.v[s][r].x / hn, y.v[s][r].y / hn);
+            for (int r = 0; r < R0; ++r) y.v[s][r] = cmul_is(y.v[s][r], sc);
           ++j;
           E::store(y, basis + (size_t)j * E::VEC);
           request(basis + (size_t)j * E::VEC, true);
