@@ -91,6 +91,9 @@ typedef struct {
   int failures;         /* solves that hit maxit */
   int failed_item;      /* first item with a failure or non-finite norm, else -1 */
   int nonfinite;        /* items stopped by a non-finite norm */
+  double alg_bytes;     /* algorithmic memory traffic of the call: 32 (I^2 + 4I + 8) bytes
+                           per grid point per solve of I iterations (two complex128
+                           surfaces, one Gram-Schmidt pass, fused H application) */
 } gqd_stats;
 
 typedef struct gqd_handle gqd_handle;

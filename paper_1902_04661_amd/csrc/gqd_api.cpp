@@ -177,6 +177,9 @@ gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
     if (s.max_iters > st->max_iters) st->max_iters = s.max_iters;
     st->failures += s.failures;
     st->nonfinite += s.nonfinite;
+    // 32 (I^2 + 4 I + 8) bytes per grid point per solve (S = 2 complex128 vectors)
+    st->alg_bytes += 32.0 * h->items[b].n *
+                     ((double)s.iterations_sq + 4.0 * (double)s.iterations + 8.0 * (double)s.solves);
     if ((s.failures || s.nonfinite) && st->failed_item < 0) st->failed_item = b;
   }
   if (st->nonfinite) return fail(GQD_ERR_NONFINITE, "a norm became non-finite (first item " +

@@ -53,7 +53,7 @@ class _Stats(ctypes.Structure):
                 ("iterations_sq", ctypes.c_longlong),
                 ("solves", ctypes.c_longlong), ("max_iters", ctypes.c_int),
                 ("failures", ctypes.c_int), ("failed_item", ctypes.c_int),
-                ("nonfinite", ctypes.c_int)]
+                ("nonfinite", ctypes.c_int), ("alg_bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -131,13 +131,14 @@ class Stats:
     failures: int
     failed_item: int
     nonfinite: int
+    alg_bytes: float
 
 
 def _stats(st) -> Optional[Stats]:
     if st is None:
         return None
     return Stats(st.h_applies, st.iterations, st.iterations_sq, st.solves, st.max_iters,
-                 st.failures, st.failed_item, st.nonfinite)
+                 st.failures, st.failed_item, st.nonfinite, st.alg_bytes)
 
 
 def _stream_ptr(stream=None):
