@@ -44,6 +44,54 @@ def alg_bytes(n: int, st) -> float:
     return 32.0 * n * (st.iterations_sq + 4 * st.iterations + 8 * st.solves)
 
 
+def ragged_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
+    """Ragged batch: seeded N in {256..4096}, centres, momenta, amplitudes; Suzuki order 6,
+    dt = 10 a.u.; one launch per grid size on forked streams per step."""
+    import torch
+    items = inputs.ragged_batch(batch, seed=0)
+    prop = gqd.from_items(items, device=dev)
+    psi = prop.pack([it.psi0 for it in items])
+    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    prop.propagate(psi, METHOD, SCHEME, 6, DT_STAR, 1, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    byts = 0.0
+    for _ in range(steps):
+        st = prop.propagate(psi, METHOD, SCHEME, 6, DT_STAR, 1, opts)
+        byts += st.alg_bytes
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pts = int(sum(it.n for it in items))
+    return {"value": pts * steps / el, "unit": "grid-point·steps/s", "ms_per_step": 1e3 * el / steps,
+            "alg_GBps": byts / el / 1e9, "hbm_frac": byts / el / 1e9 / HBM_PEAK_GBS,
+            "workload": f"{batch} packets, N in {{256..4096}} (sum {pts}), Suzuki order 6, dt={DT_STAR}"}
+
+
+def adjoint_leg(gqd, inputs, dev, batch: int, nsteps: int) -> dict:
+    """Gradients of the final surface-2 population with respect to (q0, p0, width, coupling
+    amplitude, coupling centre) per packet: forward propagation plus the reverse sweep."""
+    import torch
+    from paper_1902_04661_amd import autograd as ag
+    items = inputs.adjoint_batch(batch, seed=1, n=1024)
+    prop = gqd.from_items(items, device=dev)
+    q = ag.grid(1024, items[0].qmin, items[0].qmax, dev)
+    P = {k: torch.tensor([it.params[k] for it in items], dtype=torch.float64, device=dev, requires_grad=True)
+         for k in ["q0", "p0", "width", "amp", "center"]}
+    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi0 = torch.cat([ag.gaussian_packet(q, P["q0"][b], P["p0"][b], P["width"][b]).reshape(-1)
+                      for b in range(batch)])
+    F = torch.cat([ag.coupling(q, P["amp"][b], P["center"][b]) for b in range(batch)])
+    psiT = ag.propagate(prop, psi0, F, "suzuki", 4, 4.0, nsteps, opts)
+    L = (items[0].dq * torch.abs(psiT.reshape(batch, 2, 1024)[:, 1]) ** 2).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"value": batch / el, "unit": "gradients/s", "params_per_gradient": 5, "seconds": el,
+            "workload": f"{batch} packets, N=1024, Suzuki order 4, dt=4, {nsteps} steps, forward + reverse"}
+
+
 def cpu_leg(seconds: float = 15.0) -> dict:
     """Oracle on one core: the first packet of the batch, SZ-8 steps of dt* until ~seconds."""
     code = f"""
@@ -80,6 +128,10 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--single-steps", type=int, default=4)
+    ap.add_argument("--ragged-batch", type=int, default=4096)
+    ap.add_argument("--ragged-steps", type=int, default=2)
+    ap.add_argument("--adjoint-batch", type=int, default=256)
+    ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -166,6 +218,15 @@ def main(argv=None):
                   "workload": f"one packet q0=5 p0=0 w=0.12, N={N}, SZ-8 midpoint, dt={DT_STAR}"}
         print(f"[bench] single packet: {single['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
 
+    ragged = {}
+    if args.ragged_batch > 0 and args.ragged_steps > 0:
+        ragged = ragged_leg(gqd, inputs, dev, args.ragged_batch, args.ragged_steps)
+        print(f"[bench] ragged batch: {ragged['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
+    adjoint = {}
+    if args.adjoint_batch > 0 and args.adjoint_steps > 0:
+        adjoint = adjoint_leg(gqd, inputs, dev, args.adjoint_batch, args.adjoint_steps)
+        print(f"[bench] adjoint: {adjoint['value']:.1f} gradients/s", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_leg()
@@ -196,6 +257,8 @@ def main(argv=None):
                      "avg_launch_ms": avg_kernel_s * 1e3},
         "cpu_baseline": cpu,
         "single_packet": single,
+        "ragged_batch": ragged,
+        "adjoint": adjoint,
         "gmres": {"mean_iterations": iters / solves, "h_applies_per_step": applies / args.steps,
                   "solves_per_step": solves / args.steps},
         "check": check,
