@@ -38,6 +38,37 @@ N = 2048
 ORDER, SCHEME, METHOD = 8, "suzuki", "midp"
 TOL = 1e-14
 
+# HBM traffic of the propagation kernel from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE) over one launch from t = 0 of this workload, scaled by what the counters read
+# for a 1 GiB device copy (FETCH_SIZE 0.5x, WRITE_SIZE 1.0x of the true bytes).  Valid only
+# for the device sources it was taken on: reported as null once they change.
+TRAFFIC = {
+    "sources_sha256": "414cc0661154a41f200f09419dc6b910d59c816acce684d4c120e4ae7a527de7",
+    "fetch_kib": 144547494.125, "fetch_scale": 2.0,
+    "write_kib": 59443817.25, "write_scale": 1.0,
+    "alg_bytes_same_launch": 372962033664.0,
+    "summary": "profiles/k_run_2048_sz8_batch1024.md",
+}
+DEVICE_SOURCES = ["gqd_kernels.hip", "gqd_device.hpp", "gqd_internal.h"]
+
+
+def device_sources_sha() -> str:
+    import hashlib
+    outer = hashlib.sha256()
+    for name in DEVICE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1902_04661_amd", "csrc", name), "rb") as f:
+            outer.update((hashlib.sha256(f.read()).hexdigest() + "  paper_1902_04661_amd/csrc/"
+                          + name + "\n").encode())
+    return outer.hexdigest()
+
+
+def measured_traffic():
+    """(bytes per launch, ratio to that launch's algorithmic bytes), or (None, None)."""
+    if device_sources_sha() != TRAFFIC["sources_sha256"]:
+        return None, None
+    t = 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+    return t, t / TRAFFIC["alg_bytes_same_launch"]
+
 
 def alg_bytes(n: int, st) -> float:
     """32 (I^2 + 4I + 8) bytes per grid point per solve, summed over the solves."""
@@ -232,6 +263,7 @@ def main(argv=None):
         cpu = cpu_leg()
         print(f"[bench] cpu oracle: {cpu['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
 
+    traffic, traffic_ratio = measured_traffic() if args.batch == 1024 else (None, None)
     line = {
         "metric": METRIC,
         "value": value,
@@ -251,7 +283,9 @@ def main(argv=None):
                    "order": ORDER, "dt": DT_STAR, "gmres_tol": TOL, "restart": 32,
                    "substeps_per_step": 125, "parallelism": "one workgroup per wavepacket"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (launch from t = 0, rocprofv3 --pmc)",
+                     "traffic_over_alg_bytes": traffic_ratio,
                      "kernel": "k_run<2048> (propagate)",
                      "alg_bytes_per_launch": bytes_total / args.steps,
                      "avg_launch_ms": avg_kernel_s * 1e3},
