@@ -25,6 +25,21 @@
  * gqd_state_offset() gives each item's offset in complex elements; V uses the same
  * offsets in doubles; F and gF use half of it.
  *
+ * Two dimensions (dims = 2).  Every item is an n x n grid with one n for the whole
+ * batch, n in {64, 128, 256, 512}, on [qmin_b1, qmax_b1) x [qmin_b2, qmax_b2) with
+ * masses m_1, m_2, and H = sum_d (1/2m_d) A_d^dag A_d + V, A_d = p_d 1 - i F^(d) (the
+ * multidimensional form of Eq. 22; p_d acts along axis d as above).  Layouts, q1 the
+ * slow and q2 the fast index:
+ *   psi  complex128 [item][surface 2][n][n]
+ *   V    float64 [item][surface 2][n][n]
+ *   F    float64 [item][d 2][n][n]      (F12 along q1, then along q2)
+ *   gF   float64 [item][d 2][n][n]
+ * so V, F and gF all use the state offsets (in doubles).  A group of workgroups shares
+ * each item (cooperative launches); gqd_apply_H and gqd_diag then also need the
+ * workspace, gqd_propagate_items is unsupported.  The group crosses grid barriers with
+ * a bounded wait: if one ever times out the item stops and a call given a gqd_stats
+ * pointer returns GQD_ERR_HIP.
+ *
  * Streams and errors.  Calls are asynchronous on the given hipStream_t (NULL = the
  * null stream) unless they take a gqd_stats pointer that is not NULL: then the call
  * waits for its own work and reports GMRES failures through its return value.
@@ -64,10 +79,11 @@ typedef enum {
 } gqd_scheme;
 
 typedef struct {
-  int dims;           /* D: number of nuclear degrees of freedom; must be 1 */
+  int dims;           /* D: number of nuclear degrees of freedom, 1 or 2 */
   int surfaces;       /* S: must be 2 */
   int batch;          /* number of items, >= 1 */
-  const int* n;       /* host [batch*dims]: grid points, each one of 256, 512, 1024, 2048, 4096 */
+  const int* n;       /* host [batch*dims]: grid points per axis; 1D: each one of 256, 512,
+                         1024, 2048, 4096; 2D: all equal, one of 64, 128, 256, 512 */
   const double* qmin; /* host [batch*dims] */
   const double* qmax; /* host [batch*dims], > qmin */
   const double* mass; /* host [dims], > 0 */
@@ -107,7 +123,8 @@ void gqd_destroy(gqd_handle* h);
 gqd_status gqd_state_size(const gqd_handle* h, long long* n_complex);
 gqd_status gqd_state_offset(const gqd_handle* h, int item, long long* offset);
 
-/* Workspace for the solver: (restart + 6) state vectors.  The caller allocates it
+/* Workspace for the solver: (restart + 6) state vectors in 1D, (restart + 9) in 2D
+ * (gqd_apply_H and gqd_diag on 2D grids need it too).  The caller allocates it
  * (bytes from gqd_workspace_size) and passes it once; it must stay valid. */
 gqd_status gqd_workspace_size(const gqd_handle* h, const gqd_solver_opts* o, size_t* bytes);
 gqd_status gqd_set_workspace(gqd_handle* h, void* dev_ptr, size_t bytes);
@@ -133,7 +150,7 @@ gqd_status gqd_propagate(gqd_handle* h, gqd_method m, gqd_scheme s, int order, d
 
 /* As gqd_propagate, but item b takes its own step dt[b] and step count nsteps[b]
  * (DEVICE arrays of length batch; a negative dt propagates backward).  One launch
- * covers the whole batch, so items with different steps run side by side. */
+ * covers the whole batch, so items with different steps run side by side.  1D only. */
 gqd_status gqd_propagate_items(gqd_handle* h, gqd_method m, gqd_scheme s, int order,
                                const double* dt, const long long* nsteps, void* psi,
                                const gqd_solver_opts* o, gqd_stats* st, void* stream);
@@ -142,14 +159,15 @@ gqd_status gqd_propagate_items(gqd_handle* h, gqd_method m, gqd_scheme s, int or
  * trajectory: every substep's Cayley map is inverted exactly (time reversibility,
  * App. A, Eq. A40).  On entry psi holds psi(T) and lambda holds dL/dpsi*(T) in the
  * Euclidean sense (dL = 2 Re sum conj(lambda) dpsi); on return psi holds the
- * reconstructed psi(0), lambda holds dL/dpsi*(0), and dL/dF12 on the grid has been
- * ADDED to gF.  The same sweep serves both base methods (they share the Cayley map). */
+ * reconstructed psi(0), lambda holds dL/dpsi*(0), and dL/dF12 on the grid (2D: of each
+ * component F^(d)) has been ADDED to gF.  The same sweep serves both base methods (they share the Cayley map). */
 gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme s, int order, double dt, long long nsteps,
                        void* psi, void* lambda, double* gF, const gqd_solver_opts* o,
                        gqd_stats* st, void* stream);
 
 /* Per item: out[4b..4b+3] = (||psi||, <psi|H|psi>, P_1, P_2) with the grid inner product
- * <a|b> = dq sum conj(a) b (Sec. II.A, Eq. 6).  out: device float64 [batch*4]. */
+ * <a|b> = dq sum conj(a) b (2D: dq1 dq2 sum) (Sec. II.A, Eq. 6).  out: device float64
+ * [batch*4]. */
 gqd_status gqd_diag(gqd_handle* h, const void* psi, double* out, void* stream);
 
 /* Per item: out[2b], out[2b+1] = Re, Im <psi|phi>.  out: device float64 [batch*2]. */

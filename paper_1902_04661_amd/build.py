@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgqd.so")
-SOURCES = ["gqd_kernels.hip", "gqd_api.cpp"]
+SOURCES = ["gqd_kernels.hip", "gqd_kernels2d.hip", "gqd_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -43,8 +43,19 @@ constexpr size_t kLdsMax = 160 * 1024;
 }  // namespace
 
 struct gqd_handle {
+  int dims = 1;
   int batch = 0;
   double mass = 0.0;
+  // 2D grids (dims = 2): n x n points per item, line size class, device tables
+  int n2 = 0;
+  int line_cls = -1;
+  double mass2[2] = {0.0, 0.0};
+  std::vector<Item2> items2;
+  Item2* d_items2 = nullptr;
+  double2* d_tw2 = nullptr;
+  unsigned* d_sync = nullptr;
+  double* d_part = nullptr;
+  int resident_cap = 0;  // workgroups the partial and sync areas are sized for
   std::vector<ItemMeta> items;
   long long total_complex = 0;
   std::vector<int> class_lists[kNumClasses];
@@ -71,6 +82,13 @@ gqd_status check_opts(const gqd_handle* h, const gqd_solver_opts* o) {
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(GQD_ERR_INVALID, "tol must be finite and > 0");
   if (o->restart < 1 || o->restart > kMaxRestart) return fail(GQD_ERR_INVALID, "restart must be in 1..64");
   if (o->maxit < 1) return fail(GQD_ERR_INVALID, "maxit must be >= 1");
+  if (h->dims == 2) {
+    if (lds_bytes2(h->n2, o->restart) > kLdsMax)
+      return fail(GQD_ERR_UNSUPPORTED, "restart " + std::to_string(o->restart) +
+                                           " needs more than 160 KB of LDS at n = " + std::to_string(h->n2) +
+                                           " x " + std::to_string(h->n2));
+    return GQD_OK;
+  }
   for (int c = 0; c < kNumClasses; ++c) {
     if (!h->class_lists[c].empty() && lds_bytes(kClassN[c], o->restart) > kLdsMax)
       return fail(GQD_ERR_UNSUPPORTED, "restart " + std::to_string(o->restart) +
@@ -81,7 +99,58 @@ gqd_status check_opts(const gqd_handle* h, const gqd_solver_opts* o) {
 }
 
 size_t work_need(const gqd_handle* h, int m) {
+  if (h->dims == 2) return (size_t)h->total_complex * (size_t)(kWork2Extra + m + 1) * sizeof(double2);
   return (size_t)h->total_complex * (size_t)(m + kWorkExtra) * sizeof(double2);
+}
+
+constexpr int kSpinLimit = 1 << 22;  // polls of one grid barrier (seconds) before abort
+
+// Launch the 2D kernel over all items: groups of G workgroups per item, as many
+// items per cooperative launch as can be resident together.
+gqd_status run2d(gqd_handle* h, K2Args a, hipStream_t stream) {
+  int resident = 0;
+  GQD_HIP(max_resident2d(h->line_cls, a.sc.m, &resident));
+  if (resident < 1) return fail(GQD_ERR_UNSUPPORTED, "2D kernel cannot be resident");
+  if (resident > h->resident_cap) resident = h->resident_cap;
+  const long long vec = 2LL * h->n2 * h->n2;
+  long long gmax = 2LL * (h->n2 / kLineWaves);
+  if (vec / kThreads2 < gmax) gmax = vec / kThreads2;
+  long long per_item = resident / h->batch;
+  if (per_item < 1) per_item = 1;
+  if (per_item < gmax) gmax = per_item;
+  int G = 1;
+  while (2LL * G <= gmax) G *= 2;
+  const int per_launch = resident / G;
+  a.G = G;
+  a.work_stride = (long long)(kWork2Extra + a.sc.m + 1) * vec;
+  a.sync = h->d_sync;
+  a.part = h->d_part;
+  a.spin_limit = kSpinLimit;
+  a.tw = h->d_tw2;
+  a.V = h->V;
+  a.F = h->F;
+  a.inv2m0 = 1.0 / (2.0 * h->mass2[0]);
+  a.inv2m1 = 1.0 / (2.0 * h->mass2[1]);
+  a.mass0 = h->mass2[0];
+  a.mass1 = h->mass2[1];
+  double* out0 = a.out;
+  for (int base = 0; base < h->batch; base += per_launch) {
+    const int cnt = (h->batch - base < per_launch) ? h->batch - base : per_launch;
+    K2Args b = a;
+    b.items = h->d_items2 + base;
+    b.batch = cnt;
+    b.stats = h->d_stats + base;
+    if (out0) b.out = out0 + (a.mode == kM2Inner ? 2 : 4) * (size_t)base;
+    GQD_HIP(hipMemsetAsync(h->d_sync, 0, sizeof(unsigned) * 2 * (size_t)cnt, stream));
+    GQD_HIP(launch_run2d(h->line_cls, b, stream));
+  }
+  return GQD_OK;
+}
+
+K2Args base_args2(const gqd_handle* h) {
+  K2Args a;
+  std::memset(&a, 0, sizeof(a));
+  return a;
 }
 
 gqd_status ensure_streams(gqd_handle* h) {
@@ -178,10 +247,14 @@ gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
     st->failures += s.failures;
     st->nonfinite += s.nonfinite;
     // 32 (I^2 + 4 I + 8) bytes per grid point per solve (S = 2 complex128 vectors)
-    st->alg_bytes += 32.0 * h->items[b].n *
+    const double pts = h->dims == 2 ? (double)h->n2 * h->n2 : (double)h->items[b].n;
+    st->alg_bytes += 32.0 * pts *
                      ((double)s.iterations_sq + 4.0 * (double)s.iterations + 8.0 * (double)s.solves);
     if ((s.failures || s.nonfinite) && st->failed_item < 0) st->failed_item = b;
   }
+  for (int b = 0; b < h->batch; ++b)
+    if (h->h_stats[b].nonfinite == 2)
+      return fail(GQD_ERR_HIP, "grid barrier timed out (item " + std::to_string(b) + ")");
   if (st->nonfinite) return fail(GQD_ERR_NONFINITE, "a norm became non-finite (first item " +
                                                          std::to_string(st->failed_item) + ")");
   if (st->failures) return fail(GQD_ERR_NOT_CONVERGED, "GMRES hit maxit in " + std::to_string(st->failures) +
@@ -209,10 +282,13 @@ extern "C" {
 
 const char* gqd_last_error(void) { return g_last_error.c_str(); }
 
+static gqd_status create2d(gqd_handle** out, const gqd_grid_desc* g);
+
 gqd_status gqd_create(gqd_handle** out, const gqd_grid_desc* g) {
   if (!out || !g) return fail(GQD_ERR_INVALID, "NULL argument");
   *out = nullptr;
-  if (g->dims != 1) return fail(GQD_ERR_UNSUPPORTED, "only dims = 1 is supported");
+  if (g->dims == 2) return create2d(out, g);
+  if (g->dims != 1) return fail(GQD_ERR_UNSUPPORTED, "dims must be 1 or 2");
   if (g->surfaces != 2) return fail(GQD_ERR_UNSUPPORTED, "only surfaces = 2 is supported");
   if (g->batch < 1) return fail(GQD_ERR_INVALID, "batch must be >= 1");
   if (!g->n || !g->qmin || !g->qmax || !g->mass) return fail(GQD_ERR_INVALID, "NULL grid array");
@@ -295,8 +371,88 @@ gqd_status gqd_create(gqd_handle** out, const gqd_grid_desc* g) {
   return GQD_OK;
 }
 
+// 2D: every item is an n x n grid with the same n in {64, 128, 256, 512}; qmin, qmax
+// per item and axis, one mass per axis.
+static gqd_status create2d(gqd_handle** out, const gqd_grid_desc* g) {
+  if (g->surfaces != 2) return fail(GQD_ERR_UNSUPPORTED, "only surfaces = 2 is supported");
+  if (g->batch < 1) return fail(GQD_ERR_INVALID, "batch must be >= 1");
+  if (!g->n || !g->qmin || !g->qmax || !g->mass) return fail(GQD_ERR_INVALID, "NULL grid array");
+  for (int d = 0; d < 2; ++d)
+    if (!(g->mass[d] > 0.0) || !std::isfinite(g->mass[d])) return fail(GQD_ERR_INVALID, "mass must be > 0");
+  const int n = g->n[0];
+  int cls = -1;
+  for (int c = 0; c < kNumLine2; ++c)
+    if (kLine2N[c] == n) cls = c;
+  for (int b = 0; b < g->batch; ++b) {
+    if (g->n[2 * b] != n || g->n[2 * b + 1] != n || cls < 0)
+      return fail(GQD_ERR_UNSUPPORTED, "item " + std::to_string(b) +
+                                           ": 2D grids must be n x n with one n in {64, 128, 256, 512}");
+    for (int d = 0; d < 2; ++d) {
+      const double L = g->qmax[2 * b + d] - g->qmin[2 * b + d];
+      if (!(L > 0.0) || !std::isfinite(L))
+        return fail(GQD_ERR_INVALID, "item " + std::to_string(b) + ": qmax must exceed qmin");
+    }
+  }
+  gqd_handle* h = new (std::nothrow) gqd_handle();
+  if (!h) return fail(GQD_ERR_NOMEM, "out of host memory");
+  h->dims = 2;
+  h->batch = g->batch;
+  h->n2 = n;
+  h->line_cls = cls;
+  h->mass2[0] = g->mass[0];
+  h->mass2[1] = g->mass[1];
+  h->items2.resize(g->batch);
+  const long long vec = 2LL * n * n;
+  for (int b = 0; b < g->batch; ++b) {
+    Item2& it = h->items2[b];
+    const double L1 = g->qmax[2 * b] - g->qmin[2 * b], L2 = g->qmax[2 * b + 1] - g->qmin[2 * b + 1];
+    it.off = b * vec;
+    it.dv = (L1 / n) * (L2 / n);
+    it.ps0 = 2.0 * M_PI / L1;
+    it.ps1 = 2.0 * M_PI / L2;
+  }
+  h->total_complex = g->batch * vec;
+  h->h_stats.resize(g->batch);
+  auto cleanup = [&](gqd_status s) {
+    gqd_destroy(h);
+    return s;
+  };
+  hipError_t e;
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return cleanup(hip_fail(e, "hipGetDevice"));
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipDeviceGetAttribute"));
+  h->resident_cap = cus * (2048 / kThreads2);
+  if ((e = hipMalloc(&h->d_items2, sizeof(Item2) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc items"));
+  if ((e = hipMemcpy(h->d_items2, h->items2.data(), sizeof(Item2) * g->batch, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemcpy items"));
+  // line twiddles exp(-2 pi i t / n) in extended precision, rounded once
+  std::vector<double2> tw(n);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int t = 0; t < n; ++t) {
+    const long double ang = 2.0L * pi * (long double)t / (long double)n;
+    tw[t] = make_double2((double)cosl(ang), (double)-sinl(ang));
+  }
+  if ((e = hipMalloc(&h->d_tw2, sizeof(double2) * n)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc twiddles"));
+  if ((e = hipMemcpy(h->d_tw2, tw.data(), sizeof(double2) * n, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemcpy twiddles"));
+  if ((e = hipMalloc(&h->d_sync, sizeof(unsigned) * 2 * (size_t)h->resident_cap)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMalloc sync"));
+  if ((e = hipMalloc(&h->d_part, sizeof(double) * 2 * (size_t)h->resident_cap * kPart2)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMalloc partials"));
+  if ((e = hipMalloc(&h->d_stats, sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc stats"));
+  if ((e = hipMemset(h->d_stats, 0, sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMemset stats"));
+  if ((e = configure_kernels2d(kMaxRestart)) != hipSuccess) return cleanup(hip_fail(e, "configure kernels"));
+  *out = h;
+  return GQD_OK;
+}
+
 void gqd_destroy(gqd_handle* h) {
   if (!h) return;
+  if (h->d_items2) (void)hipFree(h->d_items2);
+  if (h->d_tw2) (void)hipFree(h->d_tw2);
+  if (h->d_sync) (void)hipFree(h->d_sync);
+  if (h->d_part) (void)hipFree(h->d_part);
   if (h->d_items) (void)hipFree(h->d_items);
   for (int c = 0; c < kNumClasses; ++c)
     if (h->d_lists[c]) (void)hipFree(h->d_lists[c]);
@@ -321,7 +477,7 @@ gqd_status gqd_state_size(const gqd_handle* h, long long* n) {
 gqd_status gqd_state_offset(const gqd_handle* h, int item, long long* off) {
   if (!h || !off) return fail(GQD_ERR_INVALID, "NULL argument");
   if (item < 0 || item >= h->batch) return fail(GQD_ERR_INVALID, "item out of range");
-  *off = h->items[item].off;
+  *off = h->dims == 2 ? h->items2[item].off : h->items[item].off;
   return GQD_OK;
 }
 
@@ -353,6 +509,16 @@ gqd_status gqd_apply_H(gqd_handle* h, const void* in, void* out, void* stream) {
   if (s != GQD_OK) return s;
   if (!in || !out) return fail(GQD_ERR_INVALID, "NULL state pointer");
   if (in == out) return fail(GQD_ERR_INVALID, "psi_in and psi_out must differ");
+  if (h->dims == 2) {
+    if (!h->work || h->work_bytes < work_need(h, 0))
+      return fail(GQD_ERR_STATE, "2D grids need the workspace (gqd_set_workspace) for gqd_apply_H");
+    K2Args a = base_args2(h);
+    a.mode = kM2ApplyH;
+    a.psi = (double2*)in;
+    a.aux = (double2*)out;
+    a.work = (double2*)h->work;
+    return run2d(h, a, (hipStream_t)stream);
+  }
   KArgs a = base_args(h);
   a.psi = (double2*)in;
   a.aux = (double2*)out;
@@ -368,6 +534,23 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   if (m != GQD_TRAP && m != GQD_MIDP) return fail(GQD_ERR_INVALID, "unknown method");
   if (!std::isfinite(dt)) return fail(GQD_ERR_INVALID, "dt must be finite");
   if (nsteps < 0) return fail(GQD_ERR_INVALID, "nsteps must be >= 0");
+  hipStream_t strm = (hipStream_t)stream;
+  if (h->dims == 2) {
+    if (dt_item || nsteps_item) return fail(GQD_ERR_UNSUPPORTED, "per-item steps are available on 1D grids");
+    K2Args a = base_args2(h);
+    s = make_gammas(sch, order, &a.gt);
+    if (s != GQD_OK) return s;
+    a.mode = kM2Propagate;
+    a.psi = (double2*)psi;
+    a.work = (double2*)h->work;
+    a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+    a.method = (m == GQD_TRAP) ? kTrap : kMidp;
+    a.dt = dt;
+    a.nsteps = nsteps;
+    s = run2d(h, a, strm);
+    if (s != GQD_OK) return s;
+    return st ? collect_stats(h, strm, st) : GQD_OK;
+  }
   KArgs a = base_args(h);
   s = make_gammas(sch, order, &a.gt);
   if (s != GQD_OK) return s;
@@ -381,7 +564,6 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   a.dt_item = dt_item;
   a.nsteps_item = nsteps_item;
   a.hpsi_valid = 0;
-  hipStream_t strm = (hipStream_t)stream;
   s = for_each_class(h, strm, a, launch_run);
   if (s != GQD_OK) return s;
   return st ? collect_stats(h, strm, st) : GQD_OK;
@@ -412,6 +594,24 @@ gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long
   if (!psi || !lambda || !gF) return fail(GQD_ERR_INVALID, "NULL pointer");
   if (!std::isfinite(dt)) return fail(GQD_ERR_INVALID, "dt must be finite");
   if (nsteps < 0) return fail(GQD_ERR_INVALID, "nsteps must be >= 0");
+  if (h->dims == 2) {
+    K2Args a = base_args2(h);
+    s = make_gammas(sch, order, &a.gt);
+    if (s != GQD_OK) return s;
+    a.mode = kM2Adjoint;
+    a.method = kMidp;
+    a.psi = (double2*)psi;
+    a.aux = (double2*)lambda;
+    a.gF = gF;
+    a.work = (double2*)h->work;
+    a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+    a.dt = dt;
+    a.nsteps = nsteps;
+    hipStream_t strm = (hipStream_t)stream;
+    s = run2d(h, a, strm);
+    if (s != GQD_OK) return s;
+    return st ? collect_stats(h, strm, st) : GQD_OK;
+  }
   KArgs a = base_args(h);
   s = make_gammas(sch, order, &a.gt);
   if (s != GQD_OK) return s;
@@ -434,6 +634,16 @@ gqd_status gqd_diag(gqd_handle* h, const void* psi, double* out, void* stream) {
   gqd_status s = ready(h, false, nullptr);
   if (s != GQD_OK) return s;
   if (!psi || !out) return fail(GQD_ERR_INVALID, "NULL pointer");
+  if (h->dims == 2) {
+    if (!h->work || h->work_bytes < work_need(h, 0))
+      return fail(GQD_ERR_STATE, "2D grids need the workspace (gqd_set_workspace) for gqd_diag");
+    K2Args a = base_args2(h);
+    a.mode = kM2Diag;
+    a.psi = (double2*)psi;
+    a.out = out;
+    a.work = (double2*)h->work;
+    return run2d(h, a, (hipStream_t)stream);
+  }
   KArgs a = base_args(h);
   a.psi = (double2*)psi;
   a.out = out;
@@ -444,6 +654,14 @@ gqd_status gqd_inner(gqd_handle* h, const void* psi, const void* phi, double* ou
   gqd_status s = ready(h, false, nullptr);
   if (s != GQD_OK) return s;
   if (!psi || !phi || !out) return fail(GQD_ERR_INVALID, "NULL pointer");
+  if (h->dims == 2) {
+    K2Args a = base_args2(h);
+    a.mode = kM2Inner;
+    a.psi = (double2*)psi;
+    a.aux = (double2*)phi;
+    a.out = out;
+    return run2d(h, a, (hipStream_t)stream);
+  }
   KArgs a = base_args(h);
   a.psi = (double2*)psi;
   a.aux = (double2*)phi;

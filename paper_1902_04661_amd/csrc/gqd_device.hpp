@@ -167,4 +167,70 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// ---------------------------------------------------------- GMRES least squares
+// The context C holds LDS arrays hcol[m+1] (new Hessenberg column), g[m+1], sn[m],
+// cs[m], y[m], R (column j at j(j+1)/2) and scal[16].
+//
+// Thread 0 applies the stored rotations to the new column, forms the new rotation
+// from (column[j], hn), stores column j of R and updates g; scal[0] = |g_(j+1)|.
+template <class C>
+__device__ void gm_givens(int j, double hn, const C& c) {
+  if (threadIdx.x == 0) {
+    GQD_L cplx* h = c.hcol;
+    for (int i = 0; i < j; ++i) {
+      const double ci = c.cs[i];
+      const cplx si = c.sn[i];
+      const cplx hi = h[i], hi1 = h[i + 1];
+      const cplx t = cadd(cscale(hi, ci), cmul(si, hi1));
+      h[i + 1] = cadd(cmul(cneg(mk(si.x, -si.y)), hi), cscale(hi1, ci));
+      h[i] = t;
+    }
+    const cplx a = h[j];
+    double cj;
+    cplx sj, rj;
+    if (hn == 0.0) {
+      cj = 1.0;
+      sj = mk(0.0, 0.0);
+      rj = a;
+    } else if (a.x == 0.0 && a.y == 0.0) {
+      cj = 0.0;
+      sj = mk(1.0, 0.0);
+      rj = mk(hn, 0.0);
+    } else {
+      const double absa = hypot(a.x, a.y);
+      const double rho = sqrt(absa * absa + hn * hn);
+      const cplx ph = mk(a.x / absa, a.y / absa);
+      cj = absa / rho;
+      sj = cscale(ph, hn / rho);
+      rj = cscale(ph, rho);
+    }
+    c.cs[j] = cj;
+    c.sn[j] = sj;
+    GQD_L cplx* Rj = c.R + (j * (j + 1)) / 2;
+    for (int i = 0; i < j; ++i) Rj[i] = h[i];
+    Rj[j] = rj;
+    const cplx gj = c.g[j];
+    c.g[j + 1] = cmul(cneg(mk(sj.x, -sj.y)), gj);
+    c.g[j] = cscale(gj, cj);
+    c.scal[0] = hypot(c.g[j + 1].x, c.g[j + 1].y);
+  }
+  __syncthreads();
+}
+
+// Thread 0: y = R^-1 g (upper triangular, k columns).
+template <class C>
+__device__ void gm_back_solve(int k, const C& c) {
+  if (threadIdx.x == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      cplx s = mk(0.0, 0.0);
+      for (int l = i + 1; l < k; ++l) s = cadd(s, cmul(c.R[(l * (l + 1)) / 2 + i], c.y[l]));
+      const cplx num = csub(c.g[i], s);
+      const cplx d = c.R[(i * (i + 1)) / 2 + i];
+      const double dd = d.x * d.x + d.y * d.y;
+      c.y[i] = mk((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd);
+    }
+  }
+  __syncthreads();
+}
+
 }  // namespace gqd

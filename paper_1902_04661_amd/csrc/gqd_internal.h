@@ -145,11 +145,74 @@ inline size_t lds_bytes(int N, int m) {
   return c * 16 + (size_t)m * 8 + 16 * 8;
 }
 
+// ------------------------------------------------------------------ 2D grids
+// A 2D item is an n x n grid (n = kLine2N[c]), state [2][n][n] with the second index
+// fastest.  A group of G workgroups shares one item: each H application runs as
+// "line blocks" (kLineWaves adjacent rows or columns, one wave per line) and every
+// vector operation on contiguous chunks of VEC / G elements, with grid barriers
+// between the phases.
+constexpr int kNumLine2 = 4;
+constexpr int kLine2N[kNumLine2] = {64, 128, 256, 512};
+constexpr int kLineWaves = 4;                   // lines per block = waves per workgroup
+constexpr int kThreads2 = 64 * kLineWaves;
+// workspace per 2D item: kWork2Extra fixed slots, then the m + 1 basis vectors
+constexpr int kWork2Extra = 8;
+// reduction slots per workgroup: m + 1 complex dots plus a few reals
+constexpr int kPart2 = 2 * (kMaxRestart + 1) + 8;
+
+struct Item2 {
+  long long off;        // state offset (complex elements) = V offset (doubles) = F offset
+  double dv;            // volume element dq1 dq2
+  double ps0, ps1;      // 2 pi / L along q1 (slow index) and q2 (fast index)
+};
+
+enum Mode2 { kM2Propagate = 0, kM2Adjoint = 1, kM2ApplyH = 2, kM2Diag = 3, kM2Inner = 4 };
+
+struct K2Args {
+  const Item2* items;
+  int batch;
+  int G;                // workgroups per item (power of two)
+  const double* V;      // [2][n][n] per item
+  const double* F;      // [2][n][n] per item: F12 along q1, along q2
+  double2* psi;
+  double2* aux;         // H psi output / lambda / second state of an inner product
+  double* gF;           // adjoint: [2][n][n] per item
+  double* out;          // diagnostics / inner product output
+  double2* work;        // (kWork2Extra + m + 1) vectors of 2 n^2 per item
+  long long work_stride;
+  const double2* tw;    // exp(-2 pi i t / n), t < n
+  double inv2m0, inv2m1;
+  double mass0, mass1;
+  SolveCfg sc;
+  int mode;
+  int method;
+  double dt;
+  long long nsteps;
+  GammaTab gt;
+  ItemStats* stats;
+  unsigned* sync;       // per item: [0] arrivals, [1] abort flag (zeroed before launch)
+  double* part;         // per item: [2][G][kPart2]
+  int spin_limit;       // polls of a grid barrier before it gives up and aborts
+};
+
+// LDS bytes of the 2D kernel at line length n and restart length m.
+inline size_t lds_bytes2(int n, int m) {
+  const size_t lines = 4 * (size_t)kLineWaves * n;  // two buffers x two surfaces per wave
+  const size_t c = lines + n + 2 * (size_t)(m + 1) + 2 * (size_t)m + (size_t)m * (m + 1) / 2 + (m + 1);
+  const size_t d = (size_t)(kLineWaves + 1) * kPart2 + m + 16;
+  return c * 16 + d * 8 + 64;
+}
+
 // Kernel launchers (gqd_kernels.hip).  Each launches one size class on `stream`.
 hipError_t launch_apply_h(int cls, const KArgs& a, hipStream_t stream);
 hipError_t launch_run(int cls, const KArgs& a, hipStream_t stream);  // propagate / adjoint
 hipError_t launch_diag(int cls, const KArgs& a, hipStream_t stream);
 hipError_t launch_inner(int cls, const KArgs& a, hipStream_t stream);
 hipError_t configure_kernels(int m_max);
+// 2D launcher (gqd_kernels2d.hip): cooperative launch of batch * G workgroups.
+hipError_t launch_run2d(int line_cls, const K2Args& a, hipStream_t stream);
+hipError_t configure_kernels2d(int m_max);
+// Most workgroups of the 2D kernel that can be resident at once on the current device.
+hipError_t max_resident2d(int line_cls, int m, int* blocks);
 
 }  // namespace gqd

@@ -413,65 +413,8 @@ struct Eng {
   }
 
   // --------------------------------------------------------------------- GMRES
-  // Thread 0 applies the stored rotations to the new Hessenberg column, forms the
-  // new rotation from (column[j], hn), stores column j of R and updates g.
-  static __device__ void givens_update(int j, double hn, const Ctx& c) {
-    if (threadIdx.x == 0) {
-      GQD_L cplx* h = c.hcol;
-      for (int i = 0; i < j; ++i) {
-        const double ci = c.cs[i];
-        const cplx si = c.sn[i];
-        const cplx hi = h[i], hi1 = h[i + 1];
-        const cplx t = cadd(cscale(hi, ci), cmul(si, hi1));
-        h[i + 1] = cadd(cmul(cneg(mk(si.x, -si.y)), hi), cscale(hi1, ci));
-        h[i] = t;
-      }
-      const cplx a = h[j];
-      double cj;
-      cplx sj, rj;
-      if (hn == 0.0) {
-        cj = 1.0;
-        sj = mk(0.0, 0.0);
-        rj = a;
-      } else if (a.x == 0.0 && a.y == 0.0) {
-        cj = 0.0;
-        sj = mk(1.0, 0.0);
-        rj = mk(hn, 0.0);
-      } else {
-        const double absa = hypot(a.x, a.y);
-        const double rho = sqrt(absa * absa + hn * hn);
-        const cplx ph = mk(a.x / absa, a.y / absa);
-        cj = absa / rho;
-        sj = cscale(ph, hn / rho);
-        rj = cscale(ph, rho);
-      }
-      c.cs[j] = cj;
-      c.sn[j] = sj;
-      GQD_L cplx* Rj = c.R + (j * (j + 1)) / 2;
-      for (int i = 0; i < j; ++i) Rj[i] = h[i];
-      Rj[j] = rj;
-      const cplx gj = c.g[j];
-      c.g[j + 1] = cmul(cneg(mk(sj.x, -sj.y)), gj);
-      c.g[j] = cscale(gj, cj);
-      c.scal[0] = hypot(c.g[j + 1].x, c.g[j + 1].y);
-    }
-    __syncthreads();
-  }
-
-  // Thread 0: y = R^-1 g (upper triangular, k columns).
-  static __device__ void back_solve(int k, const Ctx& c) {
-    if (threadIdx.x == 0) {
-      for (int i = k - 1; i >= 0; --i) {
-        cplx s = mk(0.0, 0.0);
-        for (int l = i + 1; l < k; ++l) s = cadd(s, cmul(c.R[(l * (l + 1)) / 2 + i], c.y[l]));
-        const cplx num = csub(c.g[i], s);
-        const cplx d = c.R[(i * (i + 1)) / 2 + i];
-        const double dd = d.x * d.x + d.y * d.y;
-        c.y[i] = mk((num.x * d.x + num.y * d.y) / dd, (num.y * d.x - num.x * d.y) / dd);
-      }
-    }
-    __syncthreads();
-  }
+  static __device__ void givens_update(int j, double hn, const Ctx& c) { gm_givens(j, hn, c); }
+  static __device__ void back_solve(int k, const Ctx& c) { gm_back_solve(k, c); }
 };
 
 // composition fraction tau_c: product of one gamma per level, innermost level first

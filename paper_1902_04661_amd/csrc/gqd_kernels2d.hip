@@ -1,0 +1,880 @@
+// gfx950 kernel for two-surface wavepackets on 2D grids (n x n points, q1 the slow
+// and q2 the fast index).  A 2 MB state at n = 256 does not fit one workgroup, so a
+// group of G workgroups shares one item for a whole call:
+//
+//   * H = sum_d A_d A_d / (2 m_d) + V with A_d = p_d - i F^(d) (Eq. 22 and its
+//     multidimensional form, Sec. II.E) splits into line operations: A_2 acts along
+//     rows (fixed q1), A_1 along columns (fixed q2), each line independent.  A line
+//     block is kLineWaves adjacent lines, one wave per line: the block is staged
+//     through LDS with coalesced loads, each wave runs its line's radix-4 Stockham
+//     transforms in its own LDS buffers, and the block is written back.  Row blocks
+//     also add V psi; rows and columns write two separate partial results.
+//   * every other vector operation (Gram-Schmidt, updates, norms) runs on contiguous
+//     chunks of VEC / G elements per workgroup; a reduction writes one partial per
+//     workgroup, crosses a grid barrier, and every workgroup then sums the partials
+//     in the same fixed order, so all of them take identical decisions.
+//
+// Grid barriers are an arrival counter per item; a waiting workgroup polls it a
+// bounded number of times and on time-out raises the item's abort flag, which makes
+// every workgroup of the item leave at its next barrier.  The launch is cooperative,
+// so all workgroups are resident.
+#include "gqd_device.hpp"
+#include "gqd_internal.h"
+
+namespace gqd {
+
+template <int NL>
+struct G2 {
+  static constexpr int WV = kLineWaves;
+  static constexpr int T = kThreads2;
+  static constexpr int P = NL / 64;  // points per lane per surface on a line
+  static constexpr int NPTS = NL * NL;
+  static constexpr long long VEC = 2LL * NPTS;
+  static constexpr int NBA = NL / WV;  // line blocks per axis
+  static constexpr int LOG2 = NL == 64 ? 6 : NL == 128 ? 7 : NL == 256 ? 8 : 9;
+  static constexpr int N4 = LOG2 / 2;      // radix-4 passes per transform
+  static constexpr bool ODD = LOG2 & 1;    // one radix-2 pass at the end
+  static_assert(NL % 64 == 0 && NL >= 64 && NL <= 512, "line length");
+};
+
+struct Ctx2 {
+  GQD_L cplx* lines;  // [WV][2 buffers][2 surfaces][NL]
+  GQD_L cplx* tw;     // [NL]
+  GQD_L cplx* hcol;   // [m+1]
+  GQD_L cplx* g;      // [m+1]
+  GQD_L cplx* sn;     // [m]
+  GQD_L cplx* y;      // [m]
+  GQD_L cplx* R;      // [m(m+1)/2]
+  GQD_L cplx* coef;   // [m+1]
+  GQD_L double* wpart;  // [WV][kPart2]
+  GQD_L double* red;    // [kPart2]
+  GQD_L double* cs;     // [m]
+  GQD_L double* scal;   // [16]
+};
+
+__device__ Ctx2 make_ctx2(GQD_L cplx* smem, int NL, int m) {
+  Ctx2 c;
+  c.lines = smem;
+  c.tw = c.lines + 4 * kLineWaves * NL;
+  c.hcol = c.tw + NL;
+  c.g = c.hcol + (m + 1);
+  c.sn = c.g + (m + 1);
+  c.y = c.sn + m;
+  c.R = c.y + m;
+  c.coef = c.R + (m * (m + 1)) / 2;
+  c.wpart = (GQD_L double*)(c.coef + (m + 1));
+  c.red = c.wpart + kLineWaves * kPart2;
+  c.cs = c.red + kPart2;
+  c.scal = c.cs + m;
+  return c;
+}
+
+// ------------------------------------------------------------------ grid barrier
+struct GridSync {
+  unsigned* count;
+  unsigned* abort_flag;
+  unsigned target;
+  int G;
+  int limit;
+};
+
+// Returns false (in every thread) if the item was aborted or the wait timed out.
+__device__ bool grid_barrier(GridSync& s, GQD_L double* flag) {
+  __syncthreads();
+  s.target += (unsigned)s.G;
+  if (threadIdx.x == 0) {
+    bool ok = true;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(s.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int polls = 0;
+    for (;;) {
+      const unsigned c = __hip_atomic_load(s.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((int)(c - s.target) >= 0) break;
+      if (__hip_atomic_load(s.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        ok = false;
+        break;
+      }
+      if (++polls > s.limit) {
+        __hip_atomic_store(s.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *flag = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  return uniform_d(*flag) != 0.0;
+}
+
+// ---------------------------------------------------------------- reductions
+// Wave-reduce v and record it as slot k of this workgroup's partial.
+__device__ __forceinline__ void put_partial(const Ctx2& c, int k, double v) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) c.wpart[(threadIdx.x >> 6) * kPart2 + k] = v;
+}
+
+// Sum slots 0..K-1 over the item's workgroups: c.red[k] holds the same value in every
+// workgroup afterwards.  `part` is the item's [2][G][kPart2] area; the two halves
+// alternate so that a workgroup that runs ahead never overwrites partials another
+// one is still reading.
+__device__ bool grid_sum(const Ctx2& c, GridSync& s, double* part, int& par, int g, int K) {
+  __syncthreads();
+  double* mine = part + ((size_t)par * s.G + g) * kPart2;
+  for (int k = threadIdx.x; k < K; k += kThreads2) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kLineWaves; ++w) t += c.wpart[w * kPart2 + k];
+    mine[k] = t;
+  }
+  if (!grid_barrier(s, c.scal + 15)) return false;
+  const double* all = part + (size_t)par * s.G * kPart2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int k = wave; k < K; k += kLineWaves) {
+    double t = 0.0;
+    for (int gg = lane; gg < s.G; gg += 64) t += all[(size_t)gg * kPart2 + k];
+    t = wave_sum(t);
+    if (lane == 0) c.red[k] = t;
+  }
+  __syncthreads();
+  par ^= 1;
+  return true;
+}
+
+// ------------------------------------------------------------ line transforms
+// One Stockham pass of radix R (sub-transform size Ns) over both surfaces of the
+// wave's line; S = -1 forward, +1 inverse.  With PMUL the inputs are first
+// multiplied by p_k / NL (the k-space factor of p, and the inverse's 1/NL).
+template <int NL, int R, int S, bool PMUL>
+__device__ __forceinline__ void line_pass(const GQD_L cplx* src, GQD_L cplx* dst, int Ns, const Ctx2& c,
+                                          double pn) {
+  constexpr int NR = NL / R;
+  constexpr int NB = 2 * NR;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int b0 = 0; b0 < NB; b0 += 64) {
+    const int bb = b0 + lane;
+    if (NB % 64 == 0 || bb < NB) {
+      const int s = bb / NR, j = bb % NR;
+      const int k = j & (Ns - 1);
+      const GQD_L cplx* in = src + s * NL;
+      GQD_L cplx* out = dst + s * NL;
+      cplx v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int idx = j + r * NR;
+        v[r] = in[idx];
+        if constexpr (PMUL) v[r] = cscale(v[r], pn * (double)(idx < NL / 2 ? idx : idx - NL));
+      }
+      const int step = NL / (R * Ns);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cplx t = c.tw[r * k * step];
+        if constexpr (S > 0) t.y = -t.y;
+        v[r] = cmul(v[r], t);
+      }
+      DFT<R, S>::run(v);
+      const int o = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) out[o + r * Ns] = v[r];
+    }
+  }
+}
+
+// y = IFFT(p FFT x) on the wave's line, both surfaces (x, y: lane's points lane + 64 r).
+template <int NL>
+__device__ void line_kinetic(const cplx (&x)[2][NL / 64], cplx (&y)[2][NL / 64], const Ctx2& c, double ps) {
+  using E = G2<NL>;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  GQD_L cplx* b0 = c.lines + (size_t)wave * 4 * NL;
+  GQD_L cplx* b1 = b0 + 2 * NL;
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int r = 0; r < E::P; ++r) b0[s * NL + lane + 64 * r] = x[s][r];
+  __syncthreads();
+  GQD_L cplx* src = b0;
+  GQD_L cplx* dst = b1;
+  int Ns = 1;
+#pragma unroll
+  for (int p = 0; p < E::N4; ++p) {
+    line_pass<NL, 4, -1, false>(src, dst, Ns, c, 0.0);
+    __syncthreads();
+    GQD_L cplx* t = src;
+    src = dst;
+    dst = t;
+    Ns *= 4;
+  }
+  if constexpr (E::ODD) {
+    line_pass<NL, 2, -1, false>(src, dst, Ns, c, 0.0);
+    __syncthreads();
+    GQD_L cplx* t = src;
+    src = dst;
+    dst = t;
+  }
+  const double pn = ps / (double)NL;
+  Ns = 1;
+#pragma unroll
+  for (int p = 0; p < E::N4; ++p) {
+    if (p == 0)
+      line_pass<NL, 4, 1, true>(src, dst, Ns, c, pn);
+    else
+      line_pass<NL, 4, 1, false>(src, dst, Ns, c, 0.0);
+    __syncthreads();
+    GQD_L cplx* t = src;
+    src = dst;
+    dst = t;
+    Ns *= 4;
+  }
+  if constexpr (E::ODD) {
+    line_pass<NL, 2, 1, false>(src, dst, Ns, c, 0.0);
+    __syncthreads();
+    src = dst;
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int r = 0; r < E::P; ++r) y[s][r] = src[s * NL + lane + 64 * r];
+  __syncthreads();
+}
+
+// y += -i F x coupling of A = p - i F: (A x)_1 gains -i F12 x_2, (A x)_2 gains +i F12 x_1
+template <int P>
+__device__ __forceinline__ void line_couple(cplx (&y)[2][P], const cplx (&x)[2][P], const double (&f)[P]) {
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    y[0][r] = cadd(y[0][r], mk(f[r] * x[1][r].y, -f[r] * x[1][r].x));
+    y[1][r] = cadd(y[1][r], mk(-f[r] * x[0][r].y, f[r] * x[0][r].x));
+  }
+}
+
+// Index of element (surface s, line l, point i) of a row (q1 fixed = l) or column
+// (q2 fixed = l) block, in the [2][NL][NL] layout.
+template <int NL>
+__device__ __forceinline__ int line_gidx(bool row, int s, int l, int i) {
+  return s * NL * NL + (row ? l * NL + i : i * NL + l);
+}
+// Cooperative mapping of element e of a block of kLineWaves lines onto (s, w, i):
+// rows are contiguous along i, columns along w.
+template <int NL>
+__device__ __forceinline__ void block_map(bool row, int e, int& s, int& w, int& i) {
+  s = e / (kLineWaves * NL);
+  const int rem = e - s * kLineWaves * NL;
+  if (row) {
+    w = rem / NL;
+    i = rem - w * NL;
+  } else {
+    i = rem / kLineWaves;
+    w = rem - i * kLineWaves;
+  }
+}
+
+// Line operation request of the propagation machine.
+struct LineReq {
+  const cplx* src;
+  cplx scale;        // src is multiplied by scale when `scaled`
+  bool scaled;
+  cplx* copy_dst;    // row blocks store the (scaled) source here (may be null)
+  bool opH;          // true: H parts; false: A_d x along each axis
+  cplx* out_r;       // rows:    A_2 A_2 x / (2 m_2) + V x   |  A_2 x
+  cplx* out_c;       // columns: A_1 A_1 x / (2 m_1)         |  A_1 x
+};
+
+template <int NL>
+__device__ void line_op(const LineReq& q, const Ctx2& c, const K2Args& a, const Item2& im, int g) {
+  using E = G2<NL>;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double* V = a.V + im.off;
+  const double* F = a.F + im.off;
+  for (int b = g; b < 2 * E::NBA; b += a.G) {
+    const bool row = b < E::NBA;
+    const int l0 = (row ? b : b - E::NBA) * kLineWaves;
+    for (int e = threadIdx.x; e < 2 * kLineWaves * NL; e += kThreads2) {
+      int s, w, i;
+      block_map<NL>(row, e, s, w, i);
+      const int gi = line_gidx<NL>(row, s, l0 + w, i);
+      cplx v = q.src[gi];
+      if (q.scaled) v = cmul(q.scale, v);
+      if (row && q.copy_dst) q.copy_dst[gi] = v;
+      c.lines[(size_t)w * 4 * NL + s * NL + i] = v;
+    }
+    __syncthreads();
+    const int ln = l0 + wave;
+    const GQD_L cplx* mine = c.lines + (size_t)wave * 4 * NL;
+    cplx x[2][E::P], y[2][E::P];
+    double f[E::P];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int r = 0; r < E::P; ++r) x[s][r] = mine[s * NL + lane + 64 * r];
+    const int d = row ? 1 : 0;  // rows move along q2 (F^(2)), columns along q1 (F^(1))
+#pragma unroll
+    for (int r = 0; r < E::P; ++r) f[r] = F[d * E::NPTS + line_gidx<NL>(row, 0, ln, lane + 64 * r)];
+    const double ps = row ? im.ps1 : im.ps0;
+    line_kinetic<NL>(x, y, c, ps);
+    line_couple<E::P>(y, x, f);
+    if (q.opH) {
+      cplx z[2][E::P];
+      line_kinetic<NL>(y, z, c, ps);
+      line_couple<E::P>(z, y, f);
+      const double inv2m = row ? a.inv2m1 : a.inv2m0;
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int r = 0; r < E::P; ++r) {
+          y[s][r] = cscale(z[s][r], inv2m);
+          if (row) y[s][r] = cadd(y[s][r], cscale(x[s][r], V[line_gidx<NL>(true, s, ln, lane + 64 * r)]));
+        }
+    }
+    GQD_L cplx* outl = c.lines + (size_t)wave * 4 * NL;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int r = 0; r < E::P; ++r) outl[s * NL + lane + 64 * r] = y[s][r];
+    __syncthreads();
+    cplx* out = row ? q.out_r : q.out_c;
+    for (int e = threadIdx.x; e < 2 * kLineWaves * NL; e += kThreads2) {
+      int s, w, i;
+      block_map<NL>(row, e, s, w, i);
+      out[line_gidx<NL>(row, s, l0 + w, i)] = c.lines[(size_t)w * 4 * NL + s * NL + i];
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- propagation
+enum Pc2 {
+  k2Substep,
+  k2SolveGuess,
+  k2SolveResid,
+  k2SolveArnoldi,
+  k2MidpAfter,
+  k2MidpExplicit,
+  k2TrapHpsi,
+  k2TrapAfter,
+  k2AdjAfterPhi,
+  k2AdjAfterMu,
+  k2AdjAphi,
+  k2AdjAmu,
+  k2ApplyDone,
+  k2DiagDone,
+  k2Inner
+};
+
+__device__ __forceinline__ double substep_tau2(int cc, const GammaTab& gt) {
+  double t = 1.0;
+  const int mid = gt.arity / 2;
+#pragma unroll
+  for (int l = 0; l < kMaxLevels; ++l) {
+    if (l < gt.levels) {
+      const int d = cc % gt.arity;
+      cc /= gt.arity;
+      t = (d == mid ? gt.mid[l] : gt.side[l]) * t;
+    }
+  }
+  return t;
+}
+
+// One item per group of a.G workgroups; the same machine as the 1D kernel
+// (propagation per substep of length h = tau_c dt, alpha = h/2, Sec. II.C-D; reverse
+// sweep), with the state in global memory and grid-wide reductions.
+//   midpoint (Eq. 19):  x = (1 + i alpha H)^-1 psi;  psi' = (1 - i alpha H) x, or 2x - psi
+//   trapezoid (Eq. 18): b = (1 - i alpha H) psi;     psi' = (1 + i alpha H)^-1 b
+//   reverse sweep: phi = (1 - i alpha H)^-1 psi, mu = (1 - i alpha H)^-1 lambda,
+//   psi <- 2 phi - psi, lambda <- 2 mu - lambda and, per axis d,
+//   gF_d += -(2 alpha / m_d) Re[conj(mu1)(A_d phi)2 - conj(mu2)(A_d phi)1
+//                                + conj(A_d mu)1 phi2 - conj(A_d mu)2 phi1].
+// GMRES(m) from x0 = (1 - i al H) b with an Arnoldi basis of H (classical
+// Gram-Schmidt, a second pass when the first removes more than half of |w|^2) and
+// Givens rotations on the Hessenberg matrix of 1 + i al H; stop at |g_(j+1)| <= tol |b|.
+template <int NL>
+__global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
+  using E = G2<NL>;
+  constexpr int T = kThreads2;
+  const int G = a.G;
+  const int item = blockIdx.x / G;
+  const int g = blockIdx.x - item * G;
+  if (item >= a.batch) return;
+  extern __shared__ double2 smem_raw[];
+  const int m = a.sc.m;
+  const Ctx2 c = make_ctx2((GQD_L cplx*)smem_raw, NL, m);
+  for (int t = threadIdx.x; t < NL; t += T) c.tw[t] = ((const cplx*)a.tw)[t];
+  __syncthreads();
+  const Item2 im = a.items[item];
+  cplx* psi = (cplx*)a.psi + im.off;
+  cplx* lam = (cplx*)a.aux + im.off;
+  cplx* wk = (cplx*)a.work + (size_t)item * a.work_stride;
+  cplx* X = wk;                   // solve output | phi
+  cplx* B = wk + E::VEC;          // rhs          | mu
+  cplx* HP = wk + 2 * E::VEC;     // H psi (trapezoid economy)
+  cplx* OR = wk + 3 * E::VEC;     // row part of the last H x | A_2 phi
+  cplx* OC = wk + 4 * E::VEC;     // column part              | A_1 phi
+  cplx* W = wk + 5 * E::VEC;      // unnormalised Arnoldi vector
+  cplx* AR = wk + 6 * E::VEC;     // A_2 mu
+  cplx* AC = wk + 7 * E::VEC;     // A_1 mu
+  cplx* basis = wk + kWork2Extra * E::VEC;
+  GridSync sy{a.sync + 2 * item, a.sync + 2 * item + 1, 0u, G, a.spin_limit};
+  double* part = a.part + (size_t)item * 2 * G * kPart2;
+  int par = 0;
+  const long long CH = E::VEC / G;
+  const long long e0 = (long long)g * CH, e1 = e0 + CH;
+  const long long PCH = E::NPTS / G;  // chunk of grid points (both surfaces) for the gradient
+  const long long p0 = (long long)g * PCH, p1 = p0 + PCH;
+
+  const bool adj = a.mode == kM2Adjoint;
+  const bool midp = a.method == kMidp;
+  const bool literal = a.sc.literal != 0;
+  const double dt = a.dt;
+  const long long nsteps = a.nsteps;
+
+  long long napply = 0, iters_total = 0, iters_sq = 0;
+  int solves = 0, max_iters = 0, failures = 0;
+  bool bad = false, aborted = false;
+  bool have_hpsi = false;
+  bool touched = false;  // chunk work touched global memory since the last barrier
+
+  long long n = 0;
+  int cc = adj ? a.gt.count - 1 : 0;
+  double alpha = 0.0;
+
+  bool pending = false;
+  LineReq rq{};
+  const cplx* bg = nullptr;
+  cplx* xg = nullptr;
+  double al = 0.0, tolb = 0.0;
+  int j = 0, iters = 0, after = k2Substep;
+  int pc = k2Substep;
+  if (a.mode == kM2ApplyH || a.mode == kM2Diag) {
+    rq = LineReq{psi, mk(1.0, 0.0), false, nullptr, a.mode == kM2ApplyH, OR, OC};
+    pending = true;
+    pc = a.mode == kM2ApplyH ? k2ApplyDone : k2DiagDone;
+  } else if (a.mode == kM2Inner) {
+    pc = k2Inner;
+  }
+
+  auto request = [&](const cplx* src, bool h, cplx* outr, cplx* outc) {
+    rq = LineReq{src, mk(1.0, 0.0), false, nullptr, h, outr, outc};
+    pending = true;
+  };
+  auto gsum = [&](int K) -> bool {
+    touched = false;
+    if (!grid_sum(c, sy, part, par, g, K)) {
+      aborted = true;
+      return false;
+    }
+    return true;
+  };
+  auto solve_begin = [&](const cplx* b, cplx* x, double alv, int ret) -> bool {
+    bg = b;
+    xg = x;
+    al = alv;
+    after = ret;
+    iters = 0;
+    double acc = 0.0;
+    for (long long e = e0 + threadIdx.x; e < e1; e += T) acc += cabs2(b[e]);
+    put_partial(c, 0, acc);
+    if (!gsum(1)) return false;
+    const double bnorm = sqrt(uniform_d(c.red[0]));
+    if (!isfinite(bnorm)) bad = true;
+    tolb = a.sc.tol * bnorm;
+    request(b, true, OR, OC);
+    pc = k2SolveGuess;
+    return true;
+  };
+  auto solve_end = [&](bool conv) {
+    ++solves;
+    iters_total += iters;
+    iters_sq += (long long)iters * iters;
+    if (iters > max_iters) max_iters = iters;
+    if (!conv) ++failures;
+    pc = after;
+  };
+  auto advance = [&]() {
+    if (adj) {
+      if (--cc < 0) {
+        cc = a.gt.count - 1;
+        ++n;
+      }
+    } else if (++cc == a.gt.count) {
+      cc = 0;
+      ++n;
+    }
+    pc = k2Substep;
+  };
+
+  // partial sums of <v_i, y> over this chunk, i < K, into slots 2i, 2i+1 (four basis
+  // vectors per sweep so that y is read once per four)
+  auto chunk_dots = [&](const cplx* y, int K) {
+    for (int i0 = 0; i0 < K; i0 += 4) {
+      const int nv = K - i0 < 4 ? K - i0 : 4;
+      double sx[4] = {0.0, 0.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, 0.0, 0.0};
+      for (long long e = e0 + threadIdx.x; e < e1; e += T) {
+        const cplx w = y[e];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (u < nv) {
+            const cplx z = cconjmul(basis[(size_t)(i0 + u) * E::VEC + e], w);
+            sx[u] += z.x;
+            sv[u] += z.y;
+          }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (u < nv) {
+          put_partial(c, 2 * (i0 + u), sx[u]);
+          put_partial(c, 2 * (i0 + u) + 1, sv[u]);
+        }
+    }
+  };
+  // W -= sum_i coef_i v_i over this chunk (i < K); |W|^2 into slot 0
+  auto chunk_update = [&](int K) {
+    double acc = 0.0;
+    for (long long e = e0 + threadIdx.x; e < e1; e += T) {
+      cplx w = W[e];
+      for (int i = 0; i < K; ++i) w = csub(w, cmul(c.coef[i], basis[(size_t)i * E::VEC + e]));
+      W[e] = w;
+      acc += cabs2(w);
+    }
+    put_partial(c, 0, acc);
+    touched = true;
+  };
+
+  for (;;) {
+    if (bad || aborted) break;
+    if (pending) {
+      if (touched && !grid_barrier(sy, c.scal + 15)) {
+        aborted = true;
+        break;
+      }
+      line_op<NL>(rq, c, a, im, g);
+      if (rq.opH) ++napply;
+      pending = false;
+      touched = false;
+      if (!grid_barrier(sy, c.scal + 15)) {
+        aborted = true;
+        break;
+      }
+    }
+    switch (pc) {
+      case k2Substep: {
+        if (n >= nsteps) goto done;
+        alpha = 0.5 * (substep_tau2(cc, a.gt) * dt);
+        if (adj) {
+          solve_begin(psi, X, -alpha, k2AdjAfterPhi);
+        } else if (midp) {
+          solve_begin(psi, X, alpha, k2MidpAfter);
+        } else if (literal || !have_hpsi) {
+          request(psi, true, OR, OC);
+          pc = k2TrapHpsi;
+        } else {
+          pc = k2TrapHpsi;
+        }
+        break;
+      }
+      case k2TrapHpsi: {
+        const bool fresh = literal || !have_hpsi;
+        for (long long e = e0 + threadIdx.x; e < e1; e += T) {
+          cplx h;
+          if (fresh) {
+            h = cadd(OR[e], OC[e]);
+            HP[e] = h;
+          } else {
+            h = HP[e];
+          }
+          B[e] = csub(psi[e], cmul_is(h, alpha));  // b = (1 - i alpha H) psi
+        }
+        touched = true;
+        solve_begin(B, psi, alpha, k2TrapAfter);
+        break;
+      }
+      case k2TrapAfter: {
+        if (!literal) {
+          for (long long e = e0 + threadIdx.x; e < e1; e += T) {
+            const cplx d = csub(B[e], psi[e]);  // H psi' = (b - psi') / (i alpha)
+            HP[e] = mk(d.y / alpha, -d.x / alpha);
+          }
+          touched = true;
+          have_hpsi = true;
+        }
+        advance();
+        break;
+      }
+      case k2MidpAfter: {
+        if (literal) {
+          request(X, true, OR, OC);
+          pc = k2MidpExplicit;
+          break;
+        }
+        for (long long e = e0 + threadIdx.x; e < e1; e += T) psi[e] = csub(cscale(X[e], 2.0), psi[e]);
+        touched = true;
+        advance();
+        break;
+      }
+      case k2MidpExplicit: {
+        for (long long e = e0 + threadIdx.x; e < e1; e += T)
+          psi[e] = csub(X[e], cmul_is(cadd(OR[e], OC[e]), alpha));
+        touched = true;
+        advance();
+        break;
+      }
+      case k2SolveGuess: {
+        for (long long e = e0 + threadIdx.x; e < e1; e += T)
+          xg[e] = csub(bg[e], cmul_is(cadd(OR[e], OC[e]), al));  // x0 = (1 - i al H) b
+        touched = true;
+        request(xg, true, OR, OC);
+        pc = k2SolveResid;
+        break;
+      }
+      case k2SolveResid: {
+        double acc = 0.0;
+        for (long long e = e0 + threadIdx.x; e < e1; e += T) {
+          const cplx r = csub(bg[e], cadd(xg[e], cmul_is(cadd(OR[e], OC[e]), al)));  // b - X x
+          W[e] = r;
+          acc += cabs2(r);
+        }
+        put_partial(c, 0, acc);
+        if (!gsum(1)) break;
+        const double beta = sqrt(uniform_d(c.red[0]));
+        if (!isfinite(beta)) {
+          bad = true;
+          break;
+        }
+        if (beta <= tolb) {
+          solve_end(true);
+          break;
+        }
+        if (iters >= a.sc.maxit) {
+          solve_end(false);
+          break;
+        }
+        if (threadIdx.x == 0) c.g[0] = mk(beta, 0.0);
+        // v_0 = r / beta: the H request scales the residual on the fly and row blocks
+        // store the scaled values as the first basis vector
+        rq = LineReq{W, mk(1.0 / beta, 0.0), true, basis, true, OR, OC};
+        pending = true;
+        j = 0;
+        pc = k2SolveArnoldi;
+        break;
+      }
+      case k2SolveArnoldi: {
+        ++iters;
+        // w = H v_j into W with |w|^2, then h_i = <v_i, w> for i <= j: one reduction
+        {
+          double nn = 0.0;
+          for (long long e = e0 + threadIdx.x; e < e1; e += T) {
+            const cplx w = cadd(OR[e], OC[e]);
+            W[e] = w;
+            nn += cabs2(w);
+          }
+          put_partial(c, 2 * (j + 1), nn);
+          chunk_dots(W, j + 1);
+          if (!gsum(2 * (j + 1) + 1)) break;
+        }
+        const double w2 = uniform_d(c.red[2 * (j + 1)]);
+        for (int i = threadIdx.x; i <= j; i += T) {
+          c.hcol[i] = mk(c.red[2 * i], c.red[2 * i + 1]);
+          c.coef[i] = c.hcol[i];
+        }
+        __syncthreads();
+        chunk_update(j + 1);
+        if (!gsum(1)) break;
+        double hn2 = uniform_d(c.red[0]);
+        if (hn2 < 0.5 * w2) {  // second pass ("twice is enough")
+          chunk_dots(W, j + 1);
+          if (!gsum(2 * (j + 1))) break;
+          for (int i = threadIdx.x; i <= j; i += T) {
+            c.coef[i] = mk(c.red[2 * i], c.red[2 * i + 1]);
+            c.hcol[i] = cadd(c.hcol[i], c.coef[i]);
+          }
+          __syncthreads();
+          chunk_update(j + 1);
+          if (!gsum(1)) break;
+          hn2 = uniform_d(c.red[0]);
+        }
+        const double hn = sqrt(hn2);
+        for (int i = threadIdx.x; i <= j; i += T) {
+          const cplx hx = cmul_is(c.hcol[i], al);  // i al h_ij
+          c.hcol[i] = (i == j) ? mk(1.0 + hx.x, hx.y) : hx;
+        }
+        __syncthreads();
+        gm_givens(j, fabs(al) * hn, c);
+        const double gabs = uniform_d(c.scal[0]);
+        if (!isfinite(hn) || !isfinite(gabs)) {
+          bad = true;
+          break;
+        }
+        const bool cv = gabs <= tolb;
+        if (!cv && hn != 0.0 && iters < a.sc.maxit && j + 1 < m) {
+          // v_(j+1) = i sign(al) w' / |w'|, formed while the next H application loads it
+          const double sc = (al >= 0.0 ? 1.0 : -1.0) / hn;
+          ++j;
+          rq = LineReq{W, mk(0.0, sc), true, basis + (size_t)j * E::VEC, true, OR, OC};
+          pending = true;
+          break;
+        }
+        const int k = j + 1;
+        gm_back_solve(k, c);
+        for (long long e = e0 + threadIdx.x; e < e1; e += T) {
+          cplx x = xg[e];
+          for (int i = 0; i < k; ++i) x = cadd(x, cmul(c.y[i], basis[(size_t)i * E::VEC + e]));
+          xg[e] = x;
+        }
+        touched = true;
+        if (cv) {
+          solve_end(true);
+        } else {
+          request(xg, true, OR, OC);
+          pc = k2SolveResid;
+        }
+        break;
+      }
+      case k2AdjAfterPhi:
+        solve_begin(lam, B, -alpha, k2AdjAfterMu);
+        break;
+      case k2AdjAfterMu:
+        request(X, false, OR, OC);
+        pc = k2AdjAphi;
+        break;
+      case k2AdjAphi:
+        request(B, false, AR, AC);
+        pc = k2AdjAmu;
+        break;
+      case k2AdjAmu: {
+        double* gF = a.gF + im.off;
+        const double c1 = -(2.0 * alpha / a.mass1), c0 = -(2.0 * alpha / a.mass0);
+        for (long long p = p0 + threadIdx.x; p < p1; p += T) {
+          const long long i0 = p, i1 = E::NPTS + p;
+          const cplx ph0 = X[i0], ph1 = X[i1], mu0 = B[i0], mu1 = B[i1];
+          // axis of q2 (rows): A_2 phi in OR, A_2 mu in AR; axis of q1 (columns): OC, AC
+          const double t1 = cconjmul(mu0, OR[i1]).x - cconjmul(mu1, OR[i0]).x +
+                            cconjmul(AR[i0], ph1).x - cconjmul(AR[i1], ph0).x;
+          const double t0 = cconjmul(mu0, OC[i1]).x - cconjmul(mu1, OC[i0]).x +
+                            cconjmul(AC[i0], ph1).x - cconjmul(AC[i1], ph0).x;
+          gF[p] += c0 * t0;
+          gF[E::NPTS + p] += c1 * t1;
+        }
+        for (long long e = e0 + threadIdx.x; e < e1; e += T) {
+          psi[e] = csub(cscale(X[e], 2.0), psi[e]);
+          lam[e] = csub(cscale(B[e], 2.0), lam[e]);
+        }
+        touched = true;
+        advance();
+        break;
+      }
+      case k2ApplyDone: {
+        cplx* out = (cplx*)a.aux + im.off;
+        for (long long e = e0 + threadIdx.x; e < e1; e += T) out[e] = cadd(OR[e], OC[e]);
+        goto done;
+      }
+      case k2DiagDone: {
+        // OR = A_2 psi, OC = A_1 psi
+        const double* V = a.V + im.off;
+        double q0 = 0.0, q1 = 0.0, pv = 0.0, k2 = 0.0, k1 = 0.0;
+        for (long long p = p0 + threadIdx.x; p < p1; p += T) {
+          const double a0 = cabs2(psi[p]), a1 = cabs2(psi[E::NPTS + p]);
+          q0 += a0;
+          q1 += a1;
+          pv += V[p] * a0 + V[E::NPTS + p] * a1;
+          k2 += cabs2(OR[p]) + cabs2(OR[E::NPTS + p]);
+          k1 += cabs2(OC[p]) + cabs2(OC[E::NPTS + p]);
+        }
+        put_partial(c, 0, q0);
+        put_partial(c, 1, q1);
+        put_partial(c, 2, pv);
+        put_partial(c, 3, k1);
+        put_partial(c, 4, k2);
+        if (!gsum(5)) break;
+        if (g == 0 && threadIdx.x == 0) {
+          const double P0 = c.red[0] * im.dv, P1 = c.red[1] * im.dv;
+          double* o = a.out + 4 * (size_t)item;
+          o[0] = sqrt(P0 + P1);
+          o[1] = (c.red[3] * a.inv2m0 + c.red[4] * a.inv2m1 + c.red[2]) * im.dv;
+          o[2] = P0;
+          o[3] = P1;
+        }
+        goto done;
+      }
+      case k2Inner: {
+        const cplx* y = (const cplx*)a.aux + im.off;
+        double re = 0.0, imv = 0.0;
+        for (long long e = e0 + threadIdx.x; e < e1; e += T) {
+          const cplx z = cconjmul(psi[e], y[e]);
+          re += z.x;
+          imv += z.y;
+        }
+        put_partial(c, 0, re);
+        put_partial(c, 1, imv);
+        if (!gsum(2)) break;
+        if (g == 0 && threadIdx.x == 0) {
+          a.out[2 * (size_t)item] = c.red[0] * im.dv;
+          a.out[2 * (size_t)item + 1] = c.red[1] * im.dv;
+        }
+        goto done;
+      }
+      default:
+        bad = true;
+        break;
+    }
+  }
+done:
+  if (g == 0 && threadIdx.x == 0 && a.stats) {
+    ItemStats* st = a.stats + item;
+    st->h_applies = napply;
+    st->iterations = iters_total;
+    st->iterations_sq = iters_sq;
+    st->solves = solves;
+    st->max_iters = max_iters;
+    st->failures = failures;
+    st->nonfinite = aborted ? 2 : (bad ? 1 : 0);
+  }
+}
+
+// --------------------------------------------------------------------- launchers
+
+#define GQD_DISPATCH2(cls, EXPR)                     \
+  switch (cls) {                                     \
+    case 0: { constexpr int NL = 64;  EXPR; } break; \
+    case 1: { constexpr int NL = 128; EXPR; } break; \
+    case 2: { constexpr int NL = 256; EXPR; } break; \
+    case 3: { constexpr int NL = 512; EXPR; } break; \
+    default: return hipErrorInvalidValue;            \
+  }
+
+hipError_t configure_kernels2d(int m_max) {
+  for (int cls = 0; cls < kNumLine2; ++cls) {
+    hipError_t e = hipSuccess;
+    GQD_DISPATCH2(cls, {
+      size_t bytes = lds_bytes2(NL, m_max);
+      if (bytes > 160 * 1024) bytes = 160 * 1024;
+      e = hipFuncSetAttribute((const void*)k_run2d<NL>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t max_resident2d(int cls, int m, int* blocks) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  GQD_DISPATCH2(cls, {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_run2d<NL>, kThreads2, lds_bytes2(NL, m));
+  });
+  if (e != hipSuccess) return e;
+  *blocks = per * cus;
+  return hipSuccess;
+}
+
+hipError_t launch_run2d(int cls, const K2Args& a, hipStream_t stream) {
+  K2Args args = a;
+  void* params[] = {&args};
+  GQD_DISPATCH2(cls, {
+    return hipLaunchCooperativeKernel((const void*)k_run2d<NL>, dim3(a.batch * a.G), dim3(kThreads2), params,
+                                      (unsigned)lds_bytes2(NL, a.sc.m), stream);
+  });
+  return hipSuccess;
+}
+
+}  // namespace gqd

@@ -153,6 +153,8 @@ class Propagator:
     are given as numpy arrays or device tensors and kept on the device.
     """
 
+    dims = 1
+
     def __init__(self, n: Sequence[int], qmin: Sequence[float], qmax: Sequence[float],
                  mass: float, V=None, F=None, device: str = "cuda"):
         lib = load_library()
@@ -170,18 +172,30 @@ class Propagator:
                          self.qmin.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                          self.qmax.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                          self._mass.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self._create(desc, np.concatenate([[0], np.cumsum(2 * self.n.astype(np.int64))]),
+                     [(2, int(k)) for k in self.n], V, F)
+        self.f_size = self.state_size // 2
+        self._finish_init()
+
+    def _create(self, desc, offsets, shapes, V, F):
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)))
+            _check(_lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)))
         self._h = h
         total = ctypes.c_longlong()
-        _check(lib.gqd_state_size(h, ctypes.byref(total)))
+        _check(_lib.gqd_state_size(h, ctypes.byref(total)))
         self.state_size = int(total.value)
-        self.offsets = np.concatenate([[0], np.cumsum(2 * self.n.astype(np.int64))])
+        self.offsets = offsets
+        self.shapes = shapes
         self._work = None
         self._work_m = -1
         self.V = None
         self.F = None
+        self._pending_surfaces = (V, F)
+
+    def _finish_init(self):
+        V, F = self._pending_surfaces
+        del self._pending_surfaces
         if V is not None and F is not None:
             self.set_surfaces(V, F)
 
@@ -202,10 +216,11 @@ class Propagator:
 
     def unpack(self, psi: torch.Tensor) -> List[np.ndarray]:
         host = psi.detach().cpu().numpy()
-        return [host[self.offsets[b]:self.offsets[b + 1]].reshape(2, -1) for b in range(self.batch)]
+        return [host[self.offsets[b]:self.offsets[b + 1]].reshape(self.shapes[b]) for b in range(self.batch)]
 
     def set_surfaces(self, V, F):
-        """V: per-item (2, n_b) float64 (or a flat device tensor); F: per-item (n_b,) or (1, n_b)."""
+        """V: per-item (2, *grid) float64 (or a flat device tensor); F: per-item F12 along
+        each dimension, (D, *grid) (1D also (n_b,))."""
         if isinstance(V, torch.Tensor):
             Vt = V.to(self.device, torch.float64).contiguous().reshape(-1)
         else:
@@ -214,7 +229,7 @@ class Propagator:
             Ft = F.to(self.device, torch.float64).contiguous().reshape(-1)
         else:
             Ft = torch.from_numpy(np.concatenate([np.asarray(f, np.float64).reshape(-1) for f in F])).to(self.device)
-        if Vt.numel() != self.state_size or Ft.numel() != self.state_size // 2:
+        if Vt.numel() != self.state_size or Ft.numel() != self.f_size:
             raise ValueError("V or F has the wrong size for this grid")
         self.V, self.F = Vt, Ft
         _check(_lib.gqd_set_surfaces(self._h, ctypes.c_void_p(Vt.data_ptr()), ctypes.c_void_p(Ft.data_ptr())))
@@ -238,6 +253,8 @@ class Propagator:
     # ------------------------------------------------------------------- calls
     def apply_H(self, psi: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         out = torch.empty_like(psi) if out is None else out
+        if self.dims == 2:
+            self._ensure_workspace(SolverOpts(restart=max(self._work_m, 1)))
         _check(_lib.gqd_apply_H(self._h, self._state(psi), self._state(out), _stream_ptr(stream)))
         return out
 
@@ -289,8 +306,8 @@ class Propagator:
         """In place reverse sweep: psi(T) -> psi(0), lam = dL/dpsi*(T) -> (0); gF += dL/dF12."""
         opts = opts or SolverOpts()
         self._ensure_workspace(opts)
-        if gF.dtype != torch.float64 or gF.numel() != self.state_size // 2 or not gF.is_contiguous():
-            raise ValueError("gF must be a contiguous float64 tensor with one entry per grid point")
+        if gF.dtype != torch.float64 or gF.numel() != self.f_size or not gF.is_contiguous():
+            raise ValueError("gF must be a contiguous float64 tensor with one entry per grid point and dimension")
         co = opts.c()
         st = _Stats() if stats else None
         _check(_lib.gqd_adjoint(self._h, _SCHEMES[scheme], int(order), float(dt), int(nsteps),
@@ -302,6 +319,8 @@ class Propagator:
     def diag(self, psi: torch.Tensor, stream=None) -> torch.Tensor:
         """(batch, 4): norm, energy, population of surface 1, of surface 2."""
         out = torch.empty(self.batch * 4, dtype=torch.float64, device=self.device)
+        if self.dims == 2:
+            self._ensure_workspace(SolverOpts(restart=max(self._work_m, 1)))
         _check(_lib.gqd_diag(self._h, self._state(psi), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out.reshape(self.batch, 4)
 
@@ -313,8 +332,59 @@ class Propagator:
         return torch.complex(o[:, 0], o[:, 1])
 
 
+class Propagator2D(Propagator):
+    """A batch of two-surface wavepackets on n x n grids (n in 64, 128, 256, 512).
+
+    State of one item: (2, n, n) complex128, q1 the slow and q2 the fast index.
+    qmin, qmax: (batch, 2) or (2,) bounds per item and axis; mass: (m1, m2).
+    V: per-item (2, n, n); F: per-item (2, n, n), F12 along q1 and along q2.
+    A group of workgroups shares each item; every call runs as cooperative launches.
+    """
+    dims = 2
+
+    def __init__(self, n: int, qmin, qmax, mass, V=None, F=None, batch: Optional[int] = None,
+                 device: str = "cuda"):
+        load_library()
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        qmin = np.asarray(qmin, dtype=np.float64).reshape(-1, 2)
+        qmax = np.asarray(qmax, dtype=np.float64).reshape(-1, 2)
+        self.batch = int(batch if batch is not None else max(qmin.shape[0], qmax.shape[0]))
+        self.qmin = np.ascontiguousarray(np.broadcast_to(qmin, (self.batch, 2)))
+        self.qmax = np.ascontiguousarray(np.broadcast_to(qmax, (self.batch, 2)))
+        self.n2 = int(n)
+        self.n = np.full(2 * self.batch, self.n2, dtype=np.int32)
+        self._mass = np.asarray(mass, dtype=np.float64).reshape(2).copy()
+        self.mass = tuple(float(x) for x in self._mass)
+        desc = _GridDesc(2, 2, self.batch,
+                         self.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                         self.qmin.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         self.qmax.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         self._mass.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        per = 2 * self.n2 * self.n2
+        self._create(desc, np.arange(self.batch + 1, dtype=np.int64) * per,
+                     [(2, self.n2, self.n2)] * self.batch, V, F)
+        self.f_size = self.state_size
+        self._finish_init()
+
+    def propagate_items(self, *args, **kwargs):
+        raise GqdError(-5, "per-item steps are available on 1D grids")
+
+
 def from_items(items, device: str = "cuda") -> Propagator:
-    """Propagator for a list of input items (objects with n, qmin, qmax, mass, V, F)."""
+    """Propagator for a list of input items (objects with n, qmin, qmax, mass, V, F):
+    1D items give a Propagator, 2D items (n a pair) a Propagator2D."""
+    if np.ndim(items[0].n) == 1:
+        n = {tuple(int(k) for k in it.n) for it in items}
+        masses = {tuple(float(x) for x in it.mass) for it in items}
+        if len(n) != 1 or len(masses) != 1:
+            raise ValueError("2D items must share one grid size and one pair of masses")
+        n1, n2 = n.pop()
+        if n1 != n2:
+            raise GqdError(-5, "2D grids must be n x n")
+        return Propagator2D(n1, [it.qmin for it in items], [it.qmax for it in items], masses.pop(),
+                            [it.V for it in items], [it.F for it in items], batch=len(items), device=device)
     masses = {float(it.mass) for it in items}
     if len(masses) != 1:
         raise ValueError("all items must share one mass")

@@ -51,5 +51,19 @@ def test_invalid_arguments_fail_without_a_gpu():
     mass = (ctypes.c_double * 1)(1.0)
     desc = gqd._GridDesc(1, 2, 1, n, qmin, qmax, mass)
     assert lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)) == -5   # unsupported size
-    desc = gqd._GridDesc(2, 2, 1, n, qmin, qmax, mass)
+    desc = gqd._GridDesc(3, 2, 1, n, qmin, qmax, mass)
     assert lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)) == -5   # dims
+    # 2D: n x n with n in {64, 128, 256, 512}, two masses
+    n2 = (ctypes.c_int * 2)(128, 256)
+    q0 = (ctypes.c_double * 2)(0.0, 0.0)
+    q1 = (ctypes.c_double * 2)(1.0, 1.0)
+    m2 = (ctypes.c_double * 2)(1.0, 1.0)
+    desc = gqd._GridDesc(2, 2, 1, n2, q0, q1, m2)
+    assert lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)) == -5   # not square
+    n2 = (ctypes.c_int * 2)(96, 96)
+    desc = gqd._GridDesc(2, 2, 1, n2, q0, q1, m2)
+    assert lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)) == -5   # unsupported n
+    n2 = (ctypes.c_int * 2)(64, 64)
+    m2 = (ctypes.c_double * 2)(1.0, -1.0)
+    desc = gqd._GridDesc(2, 2, 1, n2, q0, q1, m2)
+    assert lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)) == -1   # mass of the second axis
