@@ -98,6 +98,49 @@ def ragged_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
             "workload": f"{batch} packets, N in {{256..4096}} (sum {pts}), Suzuki order 6, dt={DT_STAR}"}
 
 
+def twod_leg(gqd, inputs, dev, steps: int) -> dict:
+    """256 x 256 two-surface model (vector coupling, seeded ridge), Suzuki order 8,
+    implicit midpoint, dt = 10 a.u.: one item shared by a group of workgroups."""
+    import torch
+    it = inputs.two_dim_item(256, 256)
+    prop = gqd.from_items([it], device=dev)
+    psi = prop.pack([it.psi0])
+    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    prop.propagate(psi, METHOD, SCHEME, ORDER, DT_STAR, 1, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prop.propagate(psi, METHOD, SCHEME, ORDER, DT_STAR, steps, opts)
+    el = time.perf_counter() - t0
+    return {"value": 256 * 256 * steps / el, "unit": "grid-point·steps/s", "ms_per_step": 1e3 * el / steps,
+            "mean_gmres_iterations": st.iterations / max(st.solves, 1),
+            "us_per_h_apply": 1e6 * el / max(st.h_applies, 1), "alg_GBps": st.alg_bytes / el / 1e9,
+            "workload": f"2D 256x256, Suzuki order 8 midpoint, dt={DT_STAR}, {steps} steps"}
+
+
+def adjoint2d_leg(gqd, inputs, dev, nsteps: int) -> dict:
+    """Gradient of the final surface-2 population with respect to the four coupling
+    parameters (A, c1, c2, w) on the 256 x 256 model: forward plus reverse sweep."""
+    import torch
+    from paper_1902_04661_amd import autograd as ag
+    it = inputs.two_dim_item(256, 256)
+    prop = gqd.from_items([it], device=dev)
+    Q = ag.grid2d(256, it.qmin, it.qmax, dev)
+    P = [torch.tensor(v, dtype=torch.float64, device=dev, requires_grad=True) for v in it.params["cparams"]]
+    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    dv = ((it.qmax[0] - it.qmin[0]) / 256) * ((it.qmax[1] - it.qmin[1]) / 256)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = ag.coupling_2d(Q[0], Q[1], *P).reshape(-1)
+    psiT = ag.propagate(prop, prop.pack([it.psi0]), F, "suzuki", 8, DT_STAR, nsteps, opts)
+    L = ag.surface_population(psiT.reshape(2, 256, 256), dv)
+    L.backward()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"value": 1.0 / el, "unit": "gradients/s", "params_per_gradient": 4, "seconds": el,
+            "loss": float(L.detach()), "grad": [float(p.grad) for p in P],
+            "workload": f"2D 256x256, Suzuki order 8, dt={DT_STAR}, {nsteps} steps, forward + reverse"}
+
+
 def adjoint_leg(gqd, inputs, dev, batch: int, nsteps: int) -> dict:
     """Gradients of the final surface-2 population with respect to (q0, p0, width, coupling
     amplitude, coupling centre) per packet: forward propagation plus the reverse sweep."""
@@ -163,6 +206,8 @@ def main(argv=None):
     ap.add_argument("--ragged-steps", type=int, default=2)
     ap.add_argument("--adjoint-batch", type=int, default=256)
     ap.add_argument("--adjoint-steps", type=int, default=1000)
+    ap.add_argument("--twod-steps", type=int, default=100)
+    ap.add_argument("--adjoint2d-steps", type=int, default=400)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -258,6 +303,15 @@ def main(argv=None):
         adjoint = adjoint_leg(gqd, inputs, dev, args.adjoint_batch, args.adjoint_steps)
         print(f"[bench] adjoint: {adjoint['value']:.1f} gradients/s", file=sys.stderr, flush=True)
 
+    twod = {}
+    if args.twod_steps > 0:
+        twod = twod_leg(gqd, inputs, dev, args.twod_steps)
+        print(f"[bench] 2D: {twod['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
+    adjoint2d = {}
+    if args.adjoint2d_steps > 0:
+        adjoint2d = adjoint2d_leg(gqd, inputs, dev, args.adjoint2d_steps)
+        print(f"[bench] 2D adjoint: {adjoint2d['value']:.4f} gradients/s", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_leg()
@@ -293,6 +347,8 @@ def main(argv=None):
         "single_packet": single,
         "ragged_batch": ragged,
         "adjoint": adjoint,
+        "two_dim": twod,
+        "adjoint_2d": adjoint2d,
         "gmres": {"mean_iterations": iters / solves, "h_applies_per_step": applies / args.steps,
                   "solves_per_step": solves / args.steps},
         "check": check,

@@ -75,5 +75,31 @@ def coupling(q: torch.Tensor, amp, center, cwidth: float = 0.5) -> torch.Tensor:
 
 
 def surface_population(psi: torch.Tensor, dq: float, surface: int = 1) -> torch.Tensor:
-    """dq sum |psi_surface|^2 of one item, psi of shape (2, n)."""
+    """dq sum |psi_surface|^2 of one item, psi of shape (2, n) (2D: (2, n1, n2) and the
+    volume element dq1 dq2)."""
     return dq * torch.sum(torch.abs(psi[surface]) ** 2)
+
+
+def grid2d(n: int, qmin, qmax, device):
+    """(Q1, Q2) of an n x n grid, q1 the slow index."""
+    q1 = grid(n, qmin[0], qmax[0], device)
+    q2 = grid(n, qmin[1], qmax[1], device)
+    return torch.meshgrid(q1, q2, indexing="ij")
+
+
+def coupling_2d(Q1: torch.Tensor, Q2: torch.Tensor, amp, c1, c2, w, direction=(0.8, 0.6)) -> torch.Tensor:
+    """(2, n, n): F12^(d) = amp exp(-((q1 - c1)^2 + (q2 - c2)^2) / w^2) direction_d,
+    differentiable in amp, c1, c2, w."""
+    g = amp * torch.exp(-((Q1 - c1) ** 2 + (Q2 - c2) ** 2) / (w * w))
+    return torch.stack([direction[0] * g, direction[1] * g])
+
+
+def gaussian_packet_2d(Q1: torch.Tensor, Q2: torch.Tensor, q0, p0, width) -> torch.Tensor:
+    """(2, n, n) complex128: a product Gaussian on surface index 0 (|psi|^2 has standard
+    deviations width), renormalised on the grid."""
+    dv = float((Q1[1, 0] - Q1[0, 0]) * (Q2[0, 1] - Q2[0, 0]))
+    x1, x2 = Q1 - q0[0], Q2 - q0[1]
+    g = torch.exp(torch.complex(-(x1 * x1) / (4.0 * width[0] ** 2) - (x2 * x2) / (4.0 * width[1] ** 2),
+                                p0[0] * x1 + p0[1] * x2))
+    g = g / torch.sqrt(dv * torch.sum(torch.abs(g) ** 2))
+    return torch.stack([g, torch.zeros_like(g)])
