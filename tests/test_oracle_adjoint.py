@@ -93,3 +93,42 @@ def test_adjoint_is_the_same_for_trapezoid_forward_sweep():
           - O.population_loss(m, O.propagate(m, psi0 - h * d, O.TRAP, SCHEME, ORDER, DT, NSTEPS, OPTS))[0]) / (2 * h)
     g = 2 * np.real(np.vdot(lam0.ravel(), d.ravel()))
     assert abs(g - fd) < 1e-6 * max(abs(fd), 1e-8)
+
+
+def test_two_dimensional_coupling_gradients_match_central_differences():
+    # 16 x 16 grid, distinct coupling components along q1 and q2: the sweep's dL/dF^(d)
+    # against central differences, pointwise for each component and along a random
+    # direction of both at once
+    n, L1, L2 = 16, 6.0, 5.0
+    q1 = np.arange(n) * L1 / n
+    q2 = np.arange(n) * L2 / n
+    Q1, Q2 = np.meshgrid(q1, q2, indexing="ij")
+    V = np.stack([0.2 * (Q1 - 3) ** 2 + 0.1 * (Q2 - 2.5) ** 2,
+                  0.3 + 0.1 * np.cos(2 * math.pi * Q1 / L1)])
+    g = np.exp(-((Q1 - 3.2) ** 2 + (Q2 - 2.4) ** 2))
+    F = np.stack([0.9 * g, -0.5 * g * (Q2 - 2.0)])
+    m = O.Model((n, n), (0.0, 0.0), (L1, L2), (3.0, 4.0), V, F)
+    psi0 = np.zeros((2, n, n), complex)
+    psi0[0] = np.exp(-((Q1 - 2.8) ** 2 + (Q2 - 2.5) ** 2) + 0.7j * Q1)
+    psi0 /= math.sqrt(m.dv * np.sum(np.abs(psi0) ** 2))
+    dt, nsteps = 0.5, 6
+
+    def L_of(Fx):
+        mm = O.Model(m.n, m.qmin, m.qmax, m.mass, m.V, Fx)
+        return O.population_loss(mm, O.propagate(mm, psi0, O.MIDP, SCHEME, ORDER, dt, nsteps, OPTS))[0]
+
+    psiT = O.propagate(m, psi0, O.MIDP, SCHEME, ORDER, dt, nsteps, OPTS)
+    _, lam = O.population_loss(m, psiT)
+    psiR, _, gF = O.adjoint(m, psiT, lam, SCHEME, ORDER, dt, nsteps, OPTS)
+    assert math.sqrt(abs(O.inner(m, psiR - psi0, psiR - psi0))) < 2e-12
+    h = 1e-6
+    for d in range(2):
+        j = np.unravel_index(int(np.argmax(np.abs(gF[d]))), gF[d].shape)
+        Fp, Fm = F.copy(), F.copy()
+        Fp[(d,) + j] += h
+        Fm[(d,) + j] -= h
+        fd = (L_of(Fp) - L_of(Fm)) / (2 * h)
+        assert abs(gF[(d,) + j] - fd) < 1e-5 * abs(fd)
+    D = np.random.default_rng(11).standard_normal(F.shape)
+    fd = (L_of(F + h * D) - L_of(F - h * D)) / (2 * h)
+    assert abs(float(np.sum(gF * D)) - fd) < 1e-5 * abs(fd)
