@@ -8,6 +8,11 @@ namespace gqd {
 constexpr int kMaxLevels = 4;  // compositions up to order 10
 constexpr int kMaxArity = 5;   // Suzuki fractal has 5 substeps per level
 constexpr int kMaxRestart = 64;
+// Gram-Schmidt takes a second pass when the first leaves less than this fraction of
+// |w|^2: one classical pass loses orthogonality of order eps |w| / |w'|, so above
+// 1e-2 the loss stays within ten rounding units.  (Arnoldi on the Hermitian H cancels
+// most of H v_j against v_(j-1) and v_j: a threshold of 1/2 would repeat most passes.)
+constexpr double kReorthRatio = 1e-2;
 // workspace per item: m + kWorkExtra state vectors (basis m+1, four slots, one parking slot)
 constexpr int kWorkExtra = 6;
 constexpr int kNumClasses = 5;  // N = 256, 512, 1024, 2048, 4096
@@ -82,8 +87,10 @@ struct KArgs {
   ItemStats* stats;
 };
 
-// Sizes up to this one use two LDS transform buffers (one barrier per pass).
-constexpr int kPingPongMaxN = 2048;
+// Size classes that use two LDS transform buffers (one barrier per pass, the input
+// kept in registers); the others transform in place in one buffer so that two
+// workgroups fit in a CU's LDS.
+constexpr bool kTwoBuf[kNumClasses] = {true, true, true, true, false};
 
 // Stockham plans per size class: radices (R0, R1, R2, R3); R3 = 1 means three passes.
 // T = N / R0 threads per item; every pass has 2N/R butterflies, a multiple of T.
@@ -138,9 +145,11 @@ constexpr int pass_table_offset(int cls, int pass) {
 
 // LDS bytes needed by a launch at size N with restart length m.
 inline size_t lds_bytes(int N, int m) {
-  const int T = (N == 4096) ? 512 : (N / 4);  // threads per item (N / R0 of the plan)
+  int cls = 0;
+  while (cls + 1 < kNumClasses && kClassN[cls] != N) ++cls;
+  const int T = N / kPlan[cls][0];  // threads per item
   const int W = T / 64;
-  const size_t fft = (N <= kPingPongMaxN) ? 4 * (size_t)N : 2 * (size_t)N;
+  const size_t fft = kTwoBuf[cls] ? 4 * (size_t)N : 2 * (size_t)N;
   const size_t c = fft + (size_t)W * (m + 1) + 2 * (m + 1) + 2 * (size_t)m + (size_t)m * (m + 1) / 2;
   return c * 16 + (size_t)m * 8 + 16 * 8;
 }

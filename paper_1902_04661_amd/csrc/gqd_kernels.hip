@@ -19,9 +19,15 @@ struct Eng {
   static_assert(T % 64 == 0, "whole waves only");
   static constexpr int RF = (R3 == 1) ? R2 : R3;  // radix of the fused k-space pass
   static constexpr size_t VEC = 2 * (size_t)N;    // complex elements of one state vector
-  // N <= kPingPongMaxN: two LDS transform buffers (one barrier per pass) and a
-  // quarter-period twiddle table in LDS; larger N: one buffer, table in global memory
-  static constexpr bool kPP = N <= kPingPongMaxN;
+  // two-buffer classes: ping-pong LDS transform buffers (one barrier per pass) and the
+  // operator input kept in registers; in-place classes: one buffer, the input re-read
+  // and the partial H result parked in the workspace
+  static constexpr bool kPP = kTwoBuf[CLS];
+  // waves per SIMD the register allocation must leave room for: in-place classes with
+  // four-wave workgroups run two workgroups per CU
+  static constexpr int WPE = (!kPP && T == 256) ? 2 : 1;
+  // Gram-Schmidt sweeps take two basis vectors per turn when a thread owns few points
+  static constexpr int GSV = (R0 <= 4) ? 2 : 1;
 
   struct OV {
     cplx v[2][R0];
@@ -119,8 +125,8 @@ struct Eng {
     }
     // two basis vectors per turn so that their loads and reductions overlap
 #pragma unroll 1
-    for (int i = 0; i < K; i += 2) {
-      const bool two = i + 1 < K;
+    for (int i = 0; i < K; i += GSV) {
+      const bool two = GSV == 2 && i + 1 < K;
       const GQD_G cplx* Va = opaque(basis + (size_t)i * VEC);
       const GQD_G cplx* Vb = opaque(basis + (size_t)(two ? i + 1 : i) * VEC);
       double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
@@ -129,17 +135,21 @@ struct Eng {
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
           const cplx va = Va[s * N + pt(r)];
-          const cplx vb = Vb[s * N + pt(r)];
           const cplx z = w.v[s][r];
           ax += va.x * z.x + va.y * z.y;
           ay += va.x * z.y - va.y * z.x;
-          bx += vb.x * z.x + vb.y * z.y;
-          by += vb.x * z.y - vb.y * z.x;
+          if constexpr (GSV == 2) {
+            const cplx vb = Vb[s * N + pt(r)];
+            bx += vb.x * z.x + vb.y * z.y;
+            by += vb.x * z.y - vb.y * z.x;
+          }
         }
       ax = wave_sum(ax);
       ay = wave_sum(ay);
-      bx = wave_sum(bx);
-      by = wave_sum(by);
+      if constexpr (GSV == 2) {
+        bx = wave_sum(bx);
+        by = wave_sum(by);
+      }
       if (lane == 0) {
         c.part[wv * c.kmax + i] = mk(ax, ay);
         if (two) c.part[wv * c.kmax + i + 1] = mk(bx, by);
@@ -159,8 +169,8 @@ struct Eng {
   // w -= sum_i h[i] V_i, i < K (h in LDS)
   static __device__ void block_axpy(const cplx* __restrict__ basis, const GQD_L cplx* h, int K, OV& w) {
 #pragma unroll 1
-    for (int i = 0; i < K; i += 2) {
-      const bool two = i + 1 < K;
+    for (int i = 0; i < K; i += GSV) {
+      const bool two = GSV == 2 && i + 1 < K;
       const GQD_G cplx* Va = opaque(basis + (size_t)i * VEC);
       const GQD_G cplx* Vb = opaque(basis + (size_t)(two ? i + 1 : i) * VEC);
       const cplx ha = h[i];
@@ -170,8 +180,8 @@ struct Eng {
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
           const cplx va = Va[s * N + pt(r)];
-          const cplx vb = Vb[s * N + pt(r)];
-          w.v[s][r] = csub(csub(w.v[s][r], cmul(ha, va)), cmul(hb, vb));
+          w.v[s][r] = csub(w.v[s][r], cmul(ha, va));
+          if constexpr (GSV == 2) w.v[s][r] = csub(w.v[s][r], cmul(hb, Vb[s * N + pt(r)]));
         }
     }
   }
@@ -471,7 +481,7 @@ enum Pc {
 // mu = (1 - i alpha H)^-1 lambda, psi <- 2 phi - psi, lambda <- 2 mu - lambda,
 // gF += -(2 alpha / m) Re[conj(mu1)(A phi)2 - conj(mu2)(A phi)1 + conj(A mu)1 phi2 - conj(A mu)2 phi1].
 template <int N>
-__global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
+__global__ void __launch_bounds__(Eng<N>::T) __attribute__((amdgpu_waves_per_eu(Eng<N>::WPE))) k_run(KArgs a) {
   using E = Eng<N>;
   using OV = typename E::OV;
   constexpr int R0 = E::R0;
@@ -730,7 +740,7 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
       case kSolveArnoldi: {
         // Arnoldi on H (the Krylov space of 1 + i al H is that of H): y = H v_j is
         // orthogonalised against v_0..v_j by classical Gram-Schmidt, with a second pass
-        // only when the first cancels more than half of |w|^2 ("twice is enough").
+        // only when the first cancels all but kReorthRatio of |w|^2.
         // Column j of the Hessenberg matrix of X = 1 + i al H is delta_ij + i al h_ij,
         // and v_(j+1) = i sign(al) w'/|w'| makes its subdiagonal |al| |w'| real.
         ++iters;
@@ -738,7 +748,7 @@ __global__ void __launch_bounds__(Eng<N>::T) k_run(KArgs a) {
         const double w2 = uniform_d(c.hcol[j + 1].x);
         E::block_axpy(basis, c.hcol, j + 1, y);
         double hn2 = E::block_sum1(E::norm2(y), c);
-        if (hn2 < 0.5 * w2) {
+        if (hn2 < kReorthRatio * w2) {
           E::block_dots(basis, y, j + 1, c, c.y);
           E::block_axpy(basis, c.y, j + 1, y);
           for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);

@@ -386,7 +386,7 @@ __device__ __forceinline__ double substep_tau2(int cc, const GammaTab& gt) {
 //   gF_d += -(2 alpha / m_d) Re[conj(mu1)(A_d phi)2 - conj(mu2)(A_d phi)1
 //                                + conj(A_d mu)1 phi2 - conj(A_d mu)2 phi1].
 // GMRES(m) from x0 = (1 - i al H) b with an Arnoldi basis of H (classical
-// Gram-Schmidt, a second pass when the first removes more than half of |w|^2) and
+// Gram-Schmidt, a second pass when the first removes all but kReorthRatio of |w|^2) and
 // Givens rotations on the Hessenberg matrix of 1 + i al H; stop at |g_(j+1)| <= tol |b|.
 template <int NL>
 __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
@@ -680,7 +680,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         chunk_update(j + 1);
         if (!gsum(1)) break;
         double hn2 = uniform_d(c.red[0]);
-        if (hn2 < 0.5 * w2) {  // second pass ("twice is enough")
+        if (hn2 < kReorthRatio * w2) {  // second pass
           chunk_dots(W, j + 1);
           if (!gsum(2 * (j + 1))) break;
           for (int i = threadIdx.x; i <= j; i += T) {
