@@ -195,13 +195,35 @@ struct Eng {
     return S < 0 ? cmul(x, w) : mk(x.x * w.x + x.y * w.y, x.y * w.x - x.x * w.y);
   }
 
+  // Twiddles of the butterflies this thread handles in pass P (radix R, stride Ns): the
+  // kinetic loop loads them one pass ahead, before the barrier that closes the previous
+  // pass, so their latency overlaps the wait.
+  template <int R, int Ns>
+  struct TwS {
+    static constexpr int PER = (2 * N / R) / T;
+    cplx w[PER][R - 1];
+  };
+  template <int R, int Ns, int P>
+  static __device__ __forceinline__ void tw_load(TwS<R, Ns>& t, const GQD_G cplx* tw) {
+    constexpr int OFF = pass_table_offset(CLS, P);
+    const int tid = lane_tid();
+#pragma unroll
+    for (int q = 0; q < TwS<R, Ns>::PER; ++q) {
+      const int b = tid + q * T;
+      const int k = (b % (N / R)) % Ns;
+      const GQD_G cplx* tk = tw + OFF + k * (R - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) t.w[q][r - 1] = tk[r - 1];
+    }
+  }
+
   // One Stockham pass over both surfaces, src -> dst (dst == src when in place).
   // Butterfly j (< N/R) of surface s reads x[j + r N/R], twiddles by w_{Ns R}^{r k}
   // (k = j mod Ns), applies the radix-R DFT and writes y[(j/Ns) Ns R + k + r Ns].
-  template <int R, int Ns, int S, int P>
-  static __device__ __forceinline__ void pass(const GQD_L cplx* src, GQD_L cplx* dst, const GQD_G cplx* tw) {
-    static_assert(pass_table_size(PassNR{Ns, R}) > 0, "twiddled pass");
-    constexpr int OFF = pass_table_offset(CLS, P);
+  // `next` issues the next pass's twiddle loads before the closing barrier.
+  template <int R, int Ns, int S, class Next>
+  static __device__ __forceinline__ void pass(const GQD_L cplx* src, GQD_L cplx* dst, const TwS<R, Ns>& tw,
+                                              Next&& next) {
     constexpr int NB = 2 * N / R;
     static_assert(NB % T == 0, "butterflies must be a multiple of the thread count");
     constexpr int PER = NB / T;
@@ -221,24 +243,23 @@ struct Eng {
       const int b = tid + q * T;
       const int s = b / (N / R), j = b % (N / R);
       const int k = j % Ns;
-      const GQD_G cplx* tk = tw + OFF + k * (R - 1);
 #pragma unroll
-      for (int r = 1; r < R; ++r) x[q][r] = twmul<S>(x[q][r], tk[r - 1]);
+      for (int r = 1; r < R; ++r) x[q][r] = twmul<S>(x[q][r], tw.w[q][r - 1]);
       DFT<R, S>::run(x[q]);
       const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) dst[s * N + base + r * Ns] = x[q][r];
     }
+    next();
     __syncthreads();
   }
 
   // Fused last forward pass (radix RF, Ns = N/RF), momentum multiply and first
   // inverse pass (radix RF, Ns = 1): butterfly j's forward outputs are the k-space
   // points j + r N/RF, exactly the inputs of the inverse butterfly j.
-  template <int P>
+  template <class Next>
   static __device__ __forceinline__ void fused_kspace(const GQD_L cplx* src, GQD_L cplx* dst,
-                                                      const GQD_G cplx* tw, const Ctx& c) {
-    constexpr int OFF = pass_table_offset(CLS, P);
+                                                      const TwS<RF, N / RF>& tw, const Ctx& c, Next&& next) {
     constexpr int NB = 2 * N / RF;
     static_assert(NB % T == 0, "fused pass butterflies");
     constexpr int PER = NB / T;
@@ -259,9 +280,8 @@ struct Eng {
     for (int q = 0; q < PER; ++q) {
       const int b = tid + q * T;
       const int s = b / Ns, j = b % Ns;
-      const GQD_G cplx* tk = tw + OFF + j * (RF - 1);
 #pragma unroll
-      for (int r = 1; r < RF; ++r) x[q][r] = cmul(x[q][r], tk[r - 1]);
+      for (int r = 1; r < RF; ++r) x[q][r] = cmul(x[q][r], tw.w[q][r - 1]);
       DFT<RF, -1>::run(x[q]);
 #pragma unroll
       for (int r = 0; r < RF; ++r) {
@@ -273,6 +293,7 @@ struct Eng {
 #pragma unroll
       for (int r = 0; r < RF; ++r) dst[s * N + j * RF + r] = x[q][r];
     }
+    next();
     __syncthreads();
   }
 
@@ -280,6 +301,8 @@ struct Eng {
   static __device__ void kinetic(const OV& x, OV& u, const Ctx& c) {
     GQD_L cplx* b0 = c.fft;
     GQD_L cplx* b1 = kPP ? c.fft + 2 * N : c.fft;
+    constexpr int PL = (R3 == 1) ? 3 : 5;  // table index of the last pass
+    TwS<R1, R0> t0;
     // pass A: radix R0, Ns = 1, from owned registers (butterfly j = thread)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -290,20 +313,26 @@ struct Eng {
 #pragma unroll
       for (int r = 0; r < R0; ++r) b0[s * N + lane_tid() * R0 + r] = y[r];
     }
+    tw_load<R1, R0, 0>(t0, opaque(c.tw));
     __syncthreads();
-    constexpr int PL = (R3 == 1) ? 3 : 5;  // table index of the last pass
+    TwS<R0, T> tl;
     if constexpr (R3 == 1) {
-      pass<R1, R0, -1, 0>(b0, b1, opaque(c.tw));
-      fused_kspace<1>(b1, b0, opaque(c.tw), c);
-      pass<R1, R2, +1, 2>(b0, b1, opaque(c.tw));
+      TwS<RF, N / RF> tf;
+      TwS<R1, R2> t2;
+      pass<R1, R0, -1>(b0, b1, t0, [&] { tw_load<RF, N / RF, 1>(tf, opaque(c.tw)); });
+      fused_kspace(b1, b0, tf, c, [&] { tw_load<R1, R2, 2>(t2, opaque(c.tw)); });
+      pass<R1, R2, +1>(b0, b1, t2, [&] { tw_load<R0, T, PL>(tl, opaque(c.tw)); });
     } else {
-      pass<R1, R0, -1, 0>(b0, b1, opaque(c.tw));
-      pass<R2, R0 * R1, -1, 1>(b1, b0, opaque(c.tw));
-      fused_kspace<2>(b0, b1, opaque(c.tw), c);
-      pass<R2, R3, +1, 3>(b1, b0, opaque(c.tw));
-      pass<R1, R3 * R2, +1, 4>(b0, b1, opaque(c.tw));
+      TwS<R2, R0 * R1> t1;
+      TwS<RF, N / RF> tf;
+      TwS<R2, R3> t3;
+      TwS<R1, R3 * R2> t4;
+      pass<R1, R0, -1>(b0, b1, t0, [&] { tw_load<R2, R0 * R1, 1>(t1, opaque(c.tw)); });
+      pass<R2, R0 * R1, -1>(b1, b0, t1, [&] { tw_load<RF, N / RF, 2>(tf, opaque(c.tw)); });
+      fused_kspace(b0, b1, tf, c, [&] { tw_load<R2, R3, 3>(t3, opaque(c.tw)); });
+      pass<R2, R3, +1>(b1, b0, t3, [&] { tw_load<R1, R3 * R2, 4>(t4, opaque(c.tw)); });
+      pass<R1, R3 * R2, +1>(b0, b1, t4, [&] { tw_load<R0, T, PL>(tl, opaque(c.tw)); });
     }
-    const GQD_G cplx* tl = opaque(c.tw) + pass_table_offset(CLS, PL) + lane_tid() * (R0 - 1);
     // last inverse pass: radix R0, Ns = T, butterfly j = thread -> owned points
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -311,7 +340,7 @@ struct Eng {
 #pragma unroll
       for (int r = 0; r < R0; ++r) y[r] = b1[s * N + pt(r)];
 #pragma unroll
-      for (int r = 1; r < R0; ++r) y[r] = twmul<+1>(y[r], tl[r - 1]);
+      for (int r = 1; r < R0; ++r) y[r] = twmul<+1>(y[r], tl.w[0][r - 1]);
       DFT<R0, +1>::run(y);
 #pragma unroll
       for (int r = 0; r < R0; ++r) u.v[s][r] = y[r];
