@@ -43,6 +43,9 @@
  * Streams and errors.  Calls are asynchronous on the given hipStream_t (NULL = the
  * null stream) unless they take a gqd_stats pointer that is not NULL: then the call
  * waits for its own work and reports GMRES failures through its return value.
+ * Such a call also records each item's cost, and later launches on 1D grids start
+ * the most expensive items first (workgroups are dispatched in list order and a launch
+ * lasts until its slowest CU finishes); items are independent, so no result changes.
  * Every call returns a gqd_status; on failure gqd_last_error() (thread-local) holds
  * a message.  Nothing throws across this interface.
  */

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -232,9 +233,35 @@ gqd_status make_gammas(gqd_scheme s, int order, GammaTab* gt) {
   return GQD_OK;
 }
 
+// Longest-first dispatch: the hardware starts workgroups in launch-list order and a
+// launch ends with its slowest CU, so the items measured most expensive in the last
+// call (H applications plus squared Arnoldi counts, the Gram-Schmidt part) go first.
+// Items are independent, so the order changes no result.  Called with the device idle.
+gqd_status reorder_by_cost(gqd_handle* h) {
+  if (h->dims != 1) return GQD_OK;
+  for (int c = 0; c < kNumClasses; ++c) {
+    std::vector<int>& L = h->class_lists[c];
+    if (L.size() < 2) continue;
+    auto cost = [&](int b) {
+      const ItemStats& s = h->h_stats[b];
+      return (double)s.h_applies + 0.5 * (double)s.iterations_sq;
+    };
+    std::vector<int> sorted = L;
+    std::stable_sort(sorted.begin(), sorted.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    if (sorted == L) continue;
+    L = sorted;
+    GQD_HIP(hipMemcpy(h->d_lists[c], L.data(), sizeof(int) * L.size(), hipMemcpyHostToDevice));
+  }
+  return GQD_OK;
+}
+
 gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
   GQD_HIP(hipStreamSynchronize(stream));
   GQD_HIP(hipMemcpy(h->h_stats.data(), h->d_stats, sizeof(ItemStats) * h->batch, hipMemcpyDeviceToHost));
+  {
+    const gqd_status rs = reorder_by_cost(h);
+    if (rs != GQD_OK) return rs;
+  }
   std::memset(st, 0, sizeof(*st));
   st->failed_item = -1;
   for (int b = 0; b < h->batch; ++b) {
