@@ -43,9 +43,9 @@ TOL = 1e-14
 # for a 1 GiB device copy (FETCH_SIZE 0.5x, WRITE_SIZE 1.0x of the true bytes).  Valid only
 # for the device sources it was taken on: reported as null once they change.
 TRAFFIC = {
-    "sources_sha256": "414cc0661154a41f200f09419dc6b910d59c816acce684d4c120e4ae7a527de7",
-    "fetch_kib": 144547494.125, "fetch_scale": 2.0,
-    "write_kib": 59443817.25, "write_scale": 1.0,
+    "sources_sha256": "45d72ea929937aa1c59bcca6c5b608584f20d0ac2d1c3582faa2166a64e588ac",
+    "fetch_kib": 148926835.5625, "fetch_scale": 2.0,
+    "write_kib": 59426898.0, "write_scale": 1.0,
     "alg_bytes_same_launch": 372962033664.0,
     "summary": "profiles/k_run_2048_sz8_batch1024.md",
 }
