@@ -207,6 +207,7 @@ def main(argv=None):
     ap.add_argument("--adjoint-batch", type=int, default=256)
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--twod-steps", type=int, default=100)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default transform plans")
     ap.add_argument("--adjoint2d-steps", type=int, default=400)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -240,6 +241,8 @@ def main(argv=None):
     psi0 = prop.pack([it.psi0 for it in items])
     psi = psi0.clone()
     stream = torch.cuda.current_stream()
+    plans = prop.autotune(psi, METHOD, SCHEME, 2, DT_STAR, 1, opts) if not args.no_autotune else {}
+    print(f"[bench] transform plans: {plans}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         prop.propagate(psi, METHOD, SCHEME, ORDER, DT_STAR, 1, opts)
     print(f"[bench] warmup {args.warmup} steps done, batch {args.batch}", file=sys.stderr, flush=True)
@@ -335,7 +338,8 @@ def main(argv=None):
                    "model": "two-surface NaI-like adiabatic model, N=2048 on [3,16) bohr",
                    "batch": args.batch, "n": N, "method": "implicit midpoint", "scheme": "suzuki",
                    "order": ORDER, "dt": DT_STAR, "gmres_tol": TOL, "restart": 32,
-                   "substeps_per_step": 125, "parallelism": "one workgroup per wavepacket"},
+                   "substeps_per_step": 125, "parallelism": "one workgroup per wavepacket",
+                   "transform_plan": list(plans.get(N, ())) or None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (launch from t = 0, rocprofv3 --pmc)",

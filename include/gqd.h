@@ -158,6 +158,28 @@ gqd_status gqd_propagate_items(gqd_handle* h, gqd_method m, gqd_scheme s, int or
                                const double* dt, const long long* nsteps, void* psi,
                                const gqd_solver_opts* o, gqd_stats* st, void* stream);
 
+/* Transform plans of a 1D size n: radices (R0, R1, R2, R3; R3 = 1 means three
+ * passes) of each plan, 4 ints per plan in host radices[4 * max_plans] (may be NULL),
+ * their number in *count; the first is the default.  Needs no handle or device. */
+gqd_status gqd_list_plans(int n, int* radices, int max_plans, int* count);
+
+/* Use the plan with these radices (host int[4]) for every item of size n on this
+ * handle from the next call on.  GQD_ERR_UNSUPPORTED if n has no such plan. */
+gqd_status gqd_set_plan(gqd_handle* h, int n, const int* radices);
+
+/* Transform autotuner.  Each 1D size class has several Stockham plans (radix orders
+ * and threads per item, compiled in); this times every plan that fits in LDS at this
+ * restart length on the handle's own items (nsteps composed steps of the given method
+ * and scheme per launch, three rounds, fastest launch kept) and uses the fastest plan
+ * of each class in every later call on the handle.  psi is a SCRATCH state (for
+ * example a copy of the initial state): it is propagated in place 3 x (plans) times.
+ * radices: optional host int[20]; row c (N = 256, 512, 1024, 2048, 4096) receives the
+ * chosen plan's radices (R0, R1, R2, R3; R3 = 1 means three passes), zeros for empty
+ * classes.  The results of later calls do not depend on the plan beyond rounding.
+ * Synchronous.  2D handles have nothing to tune and return GQD_OK. */
+gqd_status gqd_autotune(gqd_handle* h, gqd_method m, gqd_scheme s, int order, double dt, long long nsteps,
+                        void* psi, const gqd_solver_opts* o, int* radices, void* stream);
+
 /* Reverse sweep of gqd_propagate for a real loss L(psi(T)), with no stored
  * trajectory: every substep's Cayley map is inverted exactly (time reversibility,
  * App. A, Eq. A40).  On entry psi holds psi(T) and lambda holds dL/dpsi*(T) in the

@@ -63,7 +63,8 @@ struct gqd_handle {
   ItemMeta* d_items = nullptr;
   int* d_lists[kNumClasses] = {};
   double2* d_tw = nullptr;
-  long long tw_off[kNumClasses] = {};
+  long long tw_off[kNumPlans] = {};
+  int plan[kNumClasses] = {};  // transform plan of each size class (kPlans index)
   ItemStats* d_stats = nullptr;
   std::vector<ItemStats> h_stats;
   const double* V = nullptr;
@@ -91,7 +92,7 @@ gqd_status check_opts(const gqd_handle* h, const gqd_solver_opts* o) {
     return GQD_OK;
   }
   for (int c = 0; c < kNumClasses; ++c) {
-    if (!h->class_lists[c].empty() && lds_bytes(kClassN[c], o->restart) > kLdsMax)
+    if (!h->class_lists[c].empty() && lds_bytes(h->plan[c], o->restart) > kLdsMax)
       return fail(GQD_ERR_UNSUPPORTED, "restart " + std::to_string(o->restart) +
                                            " needs more than 160 KB of LDS at n = " +
                                            std::to_string(kClassN[c]));
@@ -176,8 +177,8 @@ gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
       if (h->class_lists[c].empty()) continue;
       a.list = h->d_lists[c];
       a.nlist = (int)h->class_lists[c].size();
-      a.tw = h->d_tw + h->tw_off[c];
-      GQD_HIP(fn(c, a, stream));
+      a.tw = h->d_tw + h->tw_off[h->plan[c]];
+      GQD_HIP(fn(h->plan[c], a, stream));
     }
     return GQD_OK;
   }
@@ -189,8 +190,8 @@ gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
     GQD_HIP(hipStreamWaitEvent(h->side[c], h->ev_fork, 0));
     a.list = h->d_lists[c];
     a.nlist = (int)h->class_lists[c].size();
-    a.tw = h->d_tw + h->tw_off[c];
-    GQD_HIP(fn(c, a, h->side[c]));
+    a.tw = h->d_tw + h->tw_off[h->plan[c]];
+    GQD_HIP(fn(h->plan[c], a, h->side[c]));
     GQD_HIP(hipEventRecord(h->ev_join[c], h->side[c]));
     GQD_HIP(hipStreamWaitEvent(stream, h->ev_join[c], 0));
   }
@@ -367,27 +368,28 @@ gqd_status gqd_create(gqd_handle** out, const gqd_grid_desc* g) {
     if ((e = hipMemcpy(h->d_lists[c], h->class_lists[c].data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup(hip_fail(e, "hipMemcpy lists"));
   }
-  // per-pass twiddle tables of every size class, evaluated in extended precision and
-  // rounded once: entry k (R - 1) + r - 1 of a pass = exp(-2 pi i r k / (Ns R))
+  // per-pass twiddle tables of every plan, evaluated in extended precision and rounded
+  // once: entry k (R - 1) + r - 1 of a pass = exp(-2 pi i r k / (Ns R))
   std::vector<double2> tw;
   const long double pi = 3.141592653589793238462643383279502884L;
-  for (int c = 0; c < kNumClasses; ++c) {
-    h->tw_off[c] = (long long)tw.size();
+  for (int p = 0; p < kNumPlans; ++p) {
+    h->tw_off[p] = (long long)tw.size();
     PassNR ps[6] = {};
-    const int np = twiddle_passes(c, ps);
-    for (int p = 0; p < np; ++p) {
-      const long double L = (long double)ps[p].Ns * ps[p].R;
-      for (int k = 0; k < ps[p].Ns; ++k)
-        for (int r = 1; r < ps[p].R; ++r) {
+    const int np = twiddle_passes(p, ps);
+    for (int q = 0; q < np; ++q) {
+      const long double L = (long double)ps[q].Ns * ps[q].R;
+      for (int k = 0; k < ps[q].Ns; ++k)
+        for (int r = 1; r < ps[q].R; ++r) {
           const long double ang = 2.0L * pi * (long double)(r * k) / L;
           tw.push_back(make_double2((double)cosl(ang), (double)-sinl(ang)));
         }
     }
-    if ((long long)tw.size() - h->tw_off[c] != class_table_size(c)) {
+    if ((long long)tw.size() - h->tw_off[p] != plan_table_size(p)) {
       gqd_destroy(h);
       return fail(GQD_ERR_INVALID, "internal: twiddle table size mismatch");
     }
   }
+  for (int c = 0; c < kNumClasses; ++c) h->plan[c] = kClassPlans[c][0];
   if ((e = hipMalloc(&h->d_tw, sizeof(double2) * tw.size())) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc twiddles"));
   if ((e = hipMemcpy(h->d_tw, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMemcpy twiddles"));
@@ -607,6 +609,108 @@ gqd_status gqd_propagate_items(gqd_handle* h, gqd_method m, gqd_scheme sch, int 
                                gqd_stats* st, void* stream) {
   if (!dt || !nsteps) return fail(GQD_ERR_INVALID, "NULL per-item dt or nsteps");
   return propagate_impl(h, m, sch, order, 0.0, 0, dt, nsteps, psi, o, st, stream);
+}
+
+gqd_status gqd_list_plans(int n, int* radices, int max_plans, int* count) {
+  if (!count) return fail(GQD_ERR_INVALID, "NULL argument");
+  const int c = class_of(n);
+  if (c < 0) return fail(GQD_ERR_UNSUPPORTED, "no 1D size class n = " + std::to_string(n));
+  int k = 0;
+  for (int i = 0; i < kMaxPlansPerClass; ++i) {
+    const int p = kClassPlans[c][i];
+    if (p < 0) continue;
+    if (radices && k < max_plans) {
+      radices[4 * k] = kPlans[p].R0;
+      radices[4 * k + 1] = kPlans[p].R1;
+      radices[4 * k + 2] = kPlans[p].R2;
+      radices[4 * k + 3] = kPlans[p].R3;
+    }
+    ++k;
+  }
+  *count = k;
+  return GQD_OK;
+}
+
+gqd_status gqd_set_plan(gqd_handle* h, int n, const int* radices) {
+  if (!h || !radices) return fail(GQD_ERR_INVALID, "NULL argument");
+  if (h->dims != 1) return fail(GQD_ERR_UNSUPPORTED, "transform plans are chosen per 1D size class");
+  const int c = class_of(n);
+  if (c < 0) return fail(GQD_ERR_UNSUPPORTED, "no 1D size class n = " + std::to_string(n));
+  for (int i = 0; i < kMaxPlansPerClass; ++i) {
+    const int p = kClassPlans[c][i];
+    if (p < 0) continue;
+    const Plan& P = kPlans[p];
+    if (P.R0 == radices[0] && P.R1 == radices[1] && P.R2 == radices[2] && P.R3 == radices[3]) {
+      h->plan[c] = p;
+      return GQD_OK;
+    }
+  }
+  return fail(GQD_ERR_UNSUPPORTED, "no plan with these radices for n = " + std::to_string(n));
+}
+
+gqd_status gqd_autotune(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, double dt, long long nsteps,
+                        void* psi, const gqd_solver_opts* o, int* radices, void* stream) {
+  gqd_status s = ready(h, true, o);
+  if (s != GQD_OK) return s;
+  if (!psi) return fail(GQD_ERR_INVALID, "NULL state pointer");
+  if (m != GQD_TRAP && m != GQD_MIDP) return fail(GQD_ERR_INVALID, "unknown method");
+  if (!std::isfinite(dt)) return fail(GQD_ERR_INVALID, "dt must be finite");
+  if (nsteps < 1) return fail(GQD_ERR_INVALID, "nsteps must be >= 1");
+  if (radices)
+    for (int i = 0; i < 4 * kNumClasses; ++i) radices[i] = 0;
+  if (h->dims != 1) return GQD_OK;  // 2D items have one line transform per size
+  KArgs a = base_args(h);
+  s = make_gammas(sch, order, &a.gt);
+  if (s != GQD_OK) return s;
+  a.psi = (double2*)psi;
+  a.work = (double2*)h->work;
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+  a.mode = 0;
+  a.method = (m == GQD_TRAP) ? kTrap : kMidp;
+  a.dt = dt;
+  a.nsteps = nsteps;
+  hipStream_t strm = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GQD_HIP(hipEventCreate(&e0));
+  GQD_HIP(hipEventCreate(&e1));
+  gqd_status result = GQD_OK;
+  for (int c = 0; c < kNumClasses && result == GQD_OK; ++c) {
+    if (h->class_lists[c].empty()) continue;
+    a.list = h->d_lists[c];
+    a.nlist = (int)h->class_lists[c].size();
+    float best[kMaxPlansPerClass];
+    for (int k = 0; k < kMaxPlansPerClass; ++k) best[k] = -1.0f;
+    // three rounds over the plans that fit in LDS, keeping each plan's fastest launch
+    for (int round = 0; round < 3 && result == GQD_OK; ++round)
+      for (int k = 0; k < kMaxPlansPerClass && result == GQD_OK; ++k) {
+        const int p = kClassPlans[c][k];
+        if (p < 0 || lds_bytes(p, o->restart) > kLdsMax) continue;
+        a.tw = h->d_tw + h->tw_off[p];
+        hipError_t e;
+        float ms = 0.0f;
+        if ((e = hipEventRecord(e0, strm)) != hipSuccess || (e = launch_run(p, a, strm)) != hipSuccess ||
+            (e = hipEventRecord(e1, strm)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+          result = hip_fail(e, "autotune launch");
+          break;
+        }
+        if (best[k] < 0.0f || ms < best[k]) best[k] = ms;
+      }
+    int pick = -1;
+    for (int k = 0; k < kMaxPlansPerClass; ++k)
+      if (best[k] >= 0.0f && (pick < 0 || best[k] < best[pick])) pick = k;
+    if (pick >= 0) h->plan[c] = kClassPlans[c][pick];
+    if (radices) {
+      const Plan& P = kPlans[h->plan[c]];
+      radices[4 * c] = P.R0;
+      radices[4 * c + 1] = P.R1;
+      radices[4 * c + 2] = P.R2;
+      radices[4 * c + 3] = P.R3;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return result;
 }
 
 gqd_status gqd_implicit_step(gqd_handle* h, gqd_method m, double dt, void* psi, const gqd_solver_opts* o,

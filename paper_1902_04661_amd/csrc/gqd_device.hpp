@@ -147,14 +147,6 @@ __device__ __forceinline__ int lane_tid() {
   return t;
 }
 
-// ------------------------------------------------------------------------ FFT plans
-template <int N> struct ClassOf;
-template <> struct ClassOf<256>  { static constexpr int v = 0; };
-template <> struct ClassOf<512>  { static constexpr int v = 1; };
-template <> struct ClassOf<1024> { static constexpr int v = 2; };
-template <> struct ClassOf<2048> { static constexpr int v = 3; };
-template <> struct ClassOf<4096> { static constexpr int v = 4; };
-
 // -------------------------------------------------------------------- reductions
 template <int T>
 struct Block {

@@ -72,7 +72,7 @@ struct KArgs {
   double* gF;           // adjoint: dL/dF12 accumulation [n] per item (foff layout)
   double* out;          // diagnostics output
   double2* work;        // workspace base, (m + kWorkExtra) vectors of 2n per item
-  const double2* tw;    // per-pass twiddle tables of this launch's size class
+  const double2* tw;    // per-pass twiddle tables of this launch's plan
   double inv2m;         // 1 / (2 mass)
   double mass;
   SolveCfg sc;
@@ -87,20 +87,36 @@ struct KArgs {
   ItemStats* stats;
 };
 
-// Size classes that use two LDS transform buffers (one barrier per pass, the input
-// kept in registers); the others transform in place in one buffer so that two
-// workgroups fit in a CU's LDS.
-constexpr bool kTwoBuf[kNumClasses] = {true, true, true, true, false};
-
-// Stockham plans per size class: radices (R0, R1, R2, R3); R3 = 1 means three passes.
-// T = N / R0 threads per item; every pass has 2N/R butterflies, a multiple of T.
-constexpr int kPlan[kNumClasses][4] = {
-    {4, 8, 8, 1},  // 256
-    {4, 8, 4, 4},  // 512
-    {4, 8, 8, 4},  // 1024
-    {4, 8, 8, 8},  // 2048
-    {8, 8, 8, 8},  // 4096
+// Stockham plans: radices (R0, R1, R2, R3) of one transform of N points (R3 = 1 means
+// three passes), T = N / R0 threads per item (every pass has 2N/R butterflies, a
+// multiple of T), and whether the transform ping-pongs between two LDS buffers (one
+// barrier per pass, the operator input kept in registers) or works in place.  Each
+// size class has one or more plans; the first is the default and gqd_autotune picks
+// among them by timing them on the caller's batch.
+struct Plan {
+  int N, R0, R1, R2, R3;
+  bool two_buf;
 };
+constexpr int kNumPlans = 11;
+constexpr Plan kPlans[kNumPlans] = {
+    {256, 4, 8, 8, 1, true},     // 0
+    {256, 4, 4, 4, 4, true},     // 1
+    {512, 4, 8, 4, 4, true},     // 2
+    {512, 8, 8, 8, 1, true},     // 3
+    {1024, 4, 8, 8, 4, true},    // 4
+    {1024, 8, 8, 4, 4, true},    // 5
+    {1024, 8, 8, 16, 1, true},   // 6
+    {2048, 4, 8, 8, 8, true},    // 7
+    {2048, 8, 8, 8, 4, true},    // 8
+    {2048, 8, 16, 16, 1, true},  // 9
+    {4096, 8, 8, 8, 8, false},   // 10
+};
+constexpr int kMaxPlansPerClass = 3;
+// plans of each size class, default first; -1 ends a list
+constexpr int kClassPlans[kNumClasses][kMaxPlansPerClass] = {
+    {0, 1, -1}, {2, 3, -1}, {4, 5, 6}, {7, 8, 9}, {10, -1, -1}};
+
+constexpr int plan_threads(int p) { return kPlans[p].N / kPlans[p].R0; }
 
 // Twiddled passes of one application of p, in execution order (the first forward pass
 // has Ns = 1 and needs none): (Ns, R) of each.  Both the host table builder and the
@@ -108,8 +124,8 @@ constexpr int kPlan[kNumClasses][4] = {
 struct PassNR {
   int Ns, R;
 };
-constexpr int twiddle_passes(int cls, PassNR* out) {
-  const int R0 = kPlan[cls][0], R1 = kPlan[cls][1], R2 = kPlan[cls][2], R3 = kPlan[cls][3];
+constexpr int twiddle_passes(int plan, PassNR* out) {
+  const int R0 = kPlans[plan].R0, R1 = kPlans[plan].R1, R2 = kPlans[plan].R2, R3 = kPlans[plan].R3;
   int n = 0;
   if (R3 == 1) {
     out[n++] = PassNR{R0, R1};            // forward
@@ -128,28 +144,26 @@ constexpr int twiddle_passes(int cls, PassNR* out) {
 }
 // Per-pass twiddle table: entry k (R - 1) + r - 1 = exp(-2 pi i r k / (Ns R)), k < Ns.
 constexpr int pass_table_size(PassNR p) { return p.Ns * (p.R - 1); }
-constexpr int class_table_size(int cls) {
+constexpr int plan_table_size(int plan) {
   PassNR ps[6] = {};
-  const int n = twiddle_passes(cls, ps);
+  const int n = twiddle_passes(plan, ps);
   int t = 0;
   for (int i = 0; i < n; ++i) t += pass_table_size(ps[i]);
   return t;
 }
-constexpr int pass_table_offset(int cls, int pass) {
+constexpr int pass_table_offset(int plan, int pass) {
   PassNR ps[6] = {};
-  twiddle_passes(cls, ps);
+  twiddle_passes(plan, ps);
   int t = 0;
   for (int i = 0; i < pass; ++i) t += pass_table_size(ps[i]);
   return t;
 }
 
-// LDS bytes needed by a launch at size N with restart length m.
-inline size_t lds_bytes(int N, int m) {
-  int cls = 0;
-  while (cls + 1 < kNumClasses && kClassN[cls] != N) ++cls;
-  const int T = N / kPlan[cls][0];  // threads per item
-  const int W = T / 64;
-  const size_t fft = kTwoBuf[cls] ? 4 * (size_t)N : 2 * (size_t)N;
+// LDS bytes needed by a launch of a plan with restart length m.
+inline size_t lds_bytes(int plan, int m) {
+  const int N = kPlans[plan].N;
+  const int W = plan_threads(plan) / 64;
+  const size_t fft = kPlans[plan].two_buf ? 4 * (size_t)N : 2 * (size_t)N;
   const size_t c = fft + (size_t)W * (m + 1) + 2 * (m + 1) + 2 * (size_t)m + (size_t)m * (m + 1) / 2;
   return c * 16 + (size_t)m * 8 + 16 * 8;
 }
@@ -212,11 +226,12 @@ inline size_t lds_bytes2(int n, int m) {
   return c * 16 + d * 8 + 64;
 }
 
-// Kernel launchers (gqd_kernels.hip).  Each launches one size class on `stream`.
-hipError_t launch_apply_h(int cls, const KArgs& a, hipStream_t stream);
-hipError_t launch_run(int cls, const KArgs& a, hipStream_t stream);  // propagate / adjoint
-hipError_t launch_diag(int cls, const KArgs& a, hipStream_t stream);
-hipError_t launch_inner(int cls, const KArgs& a, hipStream_t stream);
+// Kernel launchers (gqd_kernels.hip).  Each launches the items of a.list with one plan
+// (kPlans index) on `stream`.
+hipError_t launch_apply_h(int plan, const KArgs& a, hipStream_t stream);
+hipError_t launch_run(int plan, const KArgs& a, hipStream_t stream);  // propagate / adjoint
+hipError_t launch_diag(int plan, const KArgs& a, hipStream_t stream);
+hipError_t launch_inner(int plan, const KArgs& a, hipStream_t stream);
 hipError_t configure_kernels(int m_max);
 // 2D launcher (gqd_kernels2d.hip): cooperative launch of batch * G workgroups.
 hipError_t launch_run2d(int line_cls, const K2Args& a, hipStream_t stream);

@@ -10,10 +10,10 @@
 namespace gqd {
 
 
-template <int N>
+template <int PLAN>
 struct Eng {
-  static constexpr int CLS = ClassOf<N>::v;
-  static constexpr int R0 = kPlan[CLS][0], R1 = kPlan[CLS][1], R2 = kPlan[CLS][2], R3 = kPlan[CLS][3];
+  static constexpr int N = kPlans[PLAN].N;
+  static constexpr int R0 = kPlans[PLAN].R0, R1 = kPlans[PLAN].R1, R2 = kPlans[PLAN].R2, R3 = kPlans[PLAN].R3;
   static constexpr int T = N / R0;
   static constexpr int W = T / 64;
   static_assert(T % 64 == 0, "whole waves only");
@@ -22,7 +22,7 @@ struct Eng {
   // two-buffer classes: ping-pong LDS transform buffers (one barrier per pass) and the
   // operator input kept in registers; in-place classes: one buffer, the input re-read
   // and the partial H result parked in the workspace
-  static constexpr bool kPP = kTwoBuf[CLS];
+  static constexpr bool kPP = kPlans[PLAN].two_buf;
   // waves per SIMD the register allocation must leave room for: in-place classes with
   // four-wave workgroups run two workgroups per CU
   static constexpr int WPE = (!kPP && T == 256) ? 2 : 1;
@@ -205,7 +205,7 @@ struct Eng {
   };
   template <int R, int Ns, int P>
   static __device__ __forceinline__ void tw_load(TwS<R, Ns>& t, const GQD_G cplx* tw) {
-    constexpr int OFF = pass_table_offset(CLS, P);
+    constexpr int OFF = pass_table_offset(PLAN, P);
     const int tid = lane_tid();
 #pragma unroll
     for (int q = 0; q < TwS<R, Ns>::PER; ++q) {
@@ -509,9 +509,10 @@ enum Pc {
 // Reverse sweep, substeps in reverse order: phi = (1 - i alpha H)^-1 psi,
 // mu = (1 - i alpha H)^-1 lambda, psi <- 2 phi - psi, lambda <- 2 mu - lambda,
 // gF += -(2 alpha / m) Re[conj(mu1)(A phi)2 - conj(mu2)(A phi)1 + conj(A mu)1 phi2 - conj(A mu)2 phi1].
-template <int N>
-__global__ void __launch_bounds__(Eng<N>::T) __attribute__((amdgpu_waves_per_eu(Eng<N>::WPE))) k_run(KArgs a) {
-  using E = Eng<N>;
+template <int P>
+__global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(Eng<P>::WPE))) k_run(KArgs a) {
+  using E = Eng<P>;
+  constexpr int N = E::N;
   using OV = typename E::OV;
   constexpr int R0 = E::R0;
   constexpr int T = E::T;
@@ -893,9 +894,10 @@ done:
 }
 
 // aux = H psi; aux doubles as the parking slot of the inner A psi
-template <int N>
-__global__ void __launch_bounds__(Eng<N>::T) k_apply_h(KArgs a) {
-  using E = Eng<N>;
+template <int P>
+__global__ void __launch_bounds__(Eng<P>::T) k_apply_h(KArgs a) {
+  using E = Eng<P>;
+  constexpr int N = E::N;
   if ((int)blockIdx.x >= a.nlist) return;
   extern __shared__ double2 smem_raw[];
   GQD_L cplx* smem = (GQD_L cplx*)smem_raw;
@@ -910,9 +912,10 @@ __global__ void __launch_bounds__(Eng<N>::T) k_apply_h(KArgs a) {
 }
 
 // out[item] = (norm, energy, P1, P2); energy = ||A psi||^2 / (2m) + <psi|V psi>
-template <int N>
-__global__ void __launch_bounds__(Eng<N>::T) k_diag(KArgs a) {
-  using E = Eng<N>;
+template <int P>
+__global__ void __launch_bounds__(Eng<P>::T) k_diag(KArgs a) {
+  using E = Eng<P>;
+  constexpr int N = E::N;
   if ((int)blockIdx.x >= a.nlist) return;
   extern __shared__ double2 smem_raw[];
   GQD_L cplx* smem = (GQD_L cplx*)smem_raw;
@@ -945,9 +948,10 @@ __global__ void __launch_bounds__(Eng<N>::T) k_diag(KArgs a) {
 }
 
 // out[2 item], out[2 item + 1] = Re, Im <psi|aux> = dq * sum conj(psi) aux
-template <int N>
-__global__ void __launch_bounds__(Eng<N>::T) k_inner(KArgs a) {
-  using E = Eng<N>;
+template <int P>
+__global__ void __launch_bounds__(Eng<P>::T) k_inner(KArgs a) {
+  using E = Eng<P>;
+  constexpr int N = E::N;
   if ((int)blockIdx.x >= a.nlist) return;
   extern __shared__ double2 smem_raw[];
   GQD_L cplx* smem = (GQD_L cplx*)smem_raw;
@@ -975,32 +979,39 @@ __global__ void __launch_bounds__(Eng<N>::T) k_inner(KArgs a) {
 
 // --------------------------------------------------------------------- launchers
 
-#define GQD_DISPATCH(cls, EXPR)                      \
-  switch (cls) {                                     \
-    case 0: { constexpr int N = 256;  EXPR; } break; \
-    case 1: { constexpr int N = 512;  EXPR; } break; \
-    case 2: { constexpr int N = 1024; EXPR; } break; \
-    case 3: { constexpr int N = 2048; EXPR; } break; \
-    case 4: { constexpr int N = 4096; EXPR; } break; \
-    default: return hipErrorInvalidValue;            \
+#define GQD_DISPATCH(plan, EXPR)                 \
+  switch (plan) {                                \
+    case 0: { constexpr int P = 0; EXPR; } break;   \
+    case 1: { constexpr int P = 1; EXPR; } break;   \
+    case 2: { constexpr int P = 2; EXPR; } break;   \
+    case 3: { constexpr int P = 3; EXPR; } break;   \
+    case 4: { constexpr int P = 4; EXPR; } break;   \
+    case 5: { constexpr int P = 5; EXPR; } break;   \
+    case 6: { constexpr int P = 6; EXPR; } break;   \
+    case 7: { constexpr int P = 7; EXPR; } break;   \
+    case 8: { constexpr int P = 8; EXPR; } break;   \
+    case 9: { constexpr int P = 9; EXPR; } break;   \
+    case 10: { constexpr int P = 10; EXPR; } break; \
+    default: return hipErrorInvalidValue;        \
   }
+static_assert(kNumPlans == 11, "one dispatch case per plan");
 
-template <int N>
+template <int P>
 static hipError_t set_lds_limit(size_t bytes) {
   hipError_t e;
-  if ((e = hipFuncSetAttribute((const void*)k_apply_h<N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_run<N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_diag<N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_inner<N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if ((e = hipFuncSetAttribute((const void*)k_apply_h<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_run<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_diag<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_inner<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t configure_kernels(int m_max) {
-  for (int cls = 0; cls < kNumClasses; ++cls) {
+  for (int plan = 0; plan < kNumPlans; ++plan) {
     hipError_t e = hipSuccess;
-    GQD_DISPATCH(cls, {
-      size_t bytes = lds_bytes(N, m_max);
+    GQD_DISPATCH(plan, {
+      size_t bytes = lds_bytes(P, m_max);
       if (bytes > 160 * 1024) bytes = 160 * 1024;
-      e = set_lds_limit<N>(bytes);
+      e = set_lds_limit<P>(bytes);
     });
     if (e != hipSuccess) return e;
   }
@@ -1008,15 +1019,15 @@ hipError_t configure_kernels(int m_max) {
 }
 
 #define GQD_LAUNCH(KERNEL, M_LDS)                                                                  \
-  GQD_DISPATCH(cls, {                                                                             \
+  GQD_DISPATCH(plan, {                                                                            \
     if (a.nlist <= 0) return hipSuccess;                                                          \
-    hipLaunchKernelGGL(KERNEL<N>, dim3(a.nlist), dim3(Eng<N>::T), lds_bytes(N, M_LDS), stream, a); \
+    hipLaunchKernelGGL(KERNEL<P>, dim3(a.nlist), dim3(Eng<P>::T), lds_bytes(P, M_LDS), stream, a); \
   });                                                                                             \
   return hipGetLastError();
 
-hipError_t launch_apply_h(int cls, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_apply_h, 0) }
-hipError_t launch_run(int cls, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_run, a.sc.m) }
-hipError_t launch_diag(int cls, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_diag, 0) }
-hipError_t launch_inner(int cls, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_inner, 0) }
+hipError_t launch_apply_h(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_apply_h, 0) }
+hipError_t launch_run(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_run, a.sc.m) }
+hipError_t launch_diag(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_diag, 0) }
+hipError_t launch_inner(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_inner, 0) }
 
 }  // namespace gqd

@@ -82,6 +82,9 @@ def load_library(path: str = LIB_PATH):
         "gqd_propagate": ([vp, i, i, i, d, ll, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
         "gqd_propagate_items": ([vp, i, i, i, vp, vp, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
         "gqd_adjoint": ([vp, i, i, d, ll, vp, vp, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
+        "gqd_autotune": ([vp, i, i, i, d, ll, vp, ctypes.POINTER(_SolverOpts), vp, vp], i),
+        "gqd_list_plans": ([i, vp, i, ctypes.POINTER(i)], i),
+        "gqd_set_plan": ([vp, i, vp], i),
         "gqd_diag": ([vp, vp, vp, vp], i),
         "gqd_inner": ([vp, vp, vp, vp, vp], i),
         "gqd_last_error": ([], ctypes.c_char_p),
@@ -97,7 +100,8 @@ def load_library(path: str = LIB_PATH):
 def exported_symbols() -> List[str]:
     return ["gqd_create", "gqd_destroy", "gqd_state_size", "gqd_state_offset",
             "gqd_workspace_size", "gqd_set_workspace", "gqd_set_surfaces", "gqd_apply_H",
-            "gqd_implicit_step", "gqd_propagate", "gqd_propagate_items", "gqd_adjoint",
+            "gqd_implicit_step", "gqd_propagate", "gqd_propagate_items", "gqd_adjoint", "gqd_autotune",
+            "gqd_list_plans", "gqd_set_plan",
             "gqd_diag", "gqd_inner",
             "gqd_last_error"]
 
@@ -144,6 +148,15 @@ def _stats(st) -> Optional[Stats]:
 def _stream_ptr(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def list_plans(n: int) -> List[tuple]:
+    """Radices (R0, R1, R2, R3) of every transform plan of 1D size n, default first."""
+    load_library()
+    buf = (ctypes.c_int * 64)()
+    cnt = ctypes.c_int()
+    _check(_lib.gqd_list_plans(int(n), buf, 16, ctypes.byref(cnt)))
+    return [tuple(buf[4 * k + i] for i in range(4)) for k in range(cnt.value)]
 
 
 class Propagator:
@@ -289,6 +302,29 @@ class Propagator:
         if st is None:
             self._keep = (dt_t, ns_t)  # alive until the caller synchronises
         return _stats(st)
+
+    def set_plan(self, n: int, radices) -> None:
+        """Use the transform plan with these radices for items of size n."""
+        r = (ctypes.c_int * 4)(*[int(x) for x in radices])
+        _check(_lib.gqd_set_plan(self._h, int(n), r))
+
+    def autotune(self, psi: torch.Tensor, method="midp", scheme="suzuki", order: int = 2,
+                 dt: float = 1.0, nsteps: int = 1, opts: Optional[SolverOpts] = None, stream=None):
+        """Pick the fastest transform plan per grid size on a copy of psi (psi itself is
+        left alone); returns {N: radices} for the sizes present."""
+        opts = opts or SolverOpts()
+        self._ensure_workspace(opts)
+        scratch = psi.detach().clone()
+        co = opts.c()
+        rad = (ctypes.c_int * 20)()
+        _check(_lib.gqd_autotune(self._h, _METHODS[method], _SCHEMES[scheme], int(order), float(dt),
+                                 int(nsteps), self._state(scratch), ctypes.byref(co), rad, _stream_ptr(stream)))
+        out = {}
+        for c, n in enumerate(SIZES):
+            r = tuple(rad[4 * c + k] for k in range(4))
+            if any(r):
+                out[n] = r
+        return out
 
     def implicit_step(self, psi: torch.Tensor, method="midp", dt: float = 1.0,
                       opts: Optional[SolverOpts] = None, stats: bool = True, stream=None):

@@ -195,3 +195,51 @@ def test_nonfinite_input_is_reported(gqd):
     with pytest.raises(gqd.GqdError) as e:
         prop.propagate(psi, "midp", "suzuki", 2, 10.0, 1, gqd.SolverOpts())
     assert e.value.code == -6
+
+
+def plan_cases():
+    from paper_1902_04661_amd import gqd as g
+    try:
+        return [(n, r) for n in SIZES for r in g.list_plans(n)]
+    except RuntimeError:
+        return [(n, None) for n in SIZES]
+
+
+@pytest.mark.parametrize("n,radices", plan_cases())
+def test_every_transform_plan_matches_oracle(gqd, n, radices):
+    # each compiled Stockham plan, pinned explicitly: H application and two composed
+    # SZ-4 steps against the oracle
+    items = items_for([n, n], seed=8)
+    prop = gqd.from_items(items)
+    if radices is not None:
+        prop.set_plan(n, radices)
+    xs = [I.random_state((2, n), seed=40 + b) for b in range(2)]
+    outs = prop.unpack(prop.apply_H(prop.pack(xs)))
+    for it, x, out in zip(items, xs, outs):
+        assert rel(out, O.apply_H(O.model_from_item(it), x)) <= 1e-13
+    psi = prop.pack([it.psi0 for it in items])
+    opts = dict(tol=1e-14, restart=32)
+    prop.propagate(psi, "midp", "suzuki", 4, 10.0, 2, gqd.SolverOpts(**opts))
+    for it, out in zip(items, prop.unpack(psi)):
+        ref = O.propagate(O.model_from_item(it), it.psi0, O.MIDP, O.SUZUKI, 4, 10.0, 2, O.SolverOpts(**opts))
+        r = rel(out, ref)
+        print(f"plan {radices} n={n}: rel {r:.2e}", flush=True)
+        assert r <= 1e-12
+
+
+def test_autotune_keeps_results(gqd):
+    items = items_for([256, 512, 1024, 2048, 4096, 1024], seed=9)
+    prop = gqd.from_items(items)
+    psi = prop.pack([it.psi0 for it in items])
+    chosen = prop.autotune(psi, "midp", "suzuki", 4, 10.0, 1, gqd.SolverOpts(tol=1e-14, restart=32))
+    print(f"autotune: {chosen}", flush=True)
+    assert set(chosen) == {256, 512, 1024, 2048, 4096}
+    for n, r in chosen.items():
+        assert r in gqd.list_plans(n)
+    # psi itself untouched by the tuner; results with the tuned plans match the oracle
+    assert np.array_equal(prop.unpack(psi)[0], items[0].psi0)
+    opts = dict(tol=1e-14, restart=32)
+    prop.propagate(psi, "midp", "suzuki", 4, 10.0, 1, gqd.SolverOpts(**opts))
+    for it, out in zip(items, prop.unpack(psi)):
+        ref = O.propagate(O.model_from_item(it), it.psi0, O.MIDP, O.SUZUKI, 4, 10.0, 1, O.SolverOpts(**opts))
+        assert rel(out, ref) <= 1e-12
