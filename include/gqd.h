@@ -46,6 +46,10 @@
  * Such a call also records each item's cost, and later launches on 1D grids start
  * the most expensive items first (workgroups are dispatched in list order and a launch
  * lasts until its slowest CU finishes); items are independent, so no result changes.
+ * A 1D call with a NULL gqd_stats pointer only launches kernels and orders side
+ * streams with events, so it can be captured into a HIP graph and replayed (each
+ * replay advances the captured state in place); 2D calls launch cooperatively and are
+ * not capture-safe.
  * Every call returns a gqd_status; on failure gqd_last_error() (thread-local) holds
  * a message.  Nothing throws across this interface.
  */
