@@ -130,7 +130,7 @@ void gqd_destroy(gqd_handle* h);
 gqd_status gqd_state_size(const gqd_handle* h, long long* n_complex);
 gqd_status gqd_state_offset(const gqd_handle* h, int item, long long* offset);
 
-/* Workspace for the solver: (restart + 6) state vectors in 1D, (restart + 9) in 2D
+/* Workspace for the solver: (restart + 6) state vectors in 1D, (restart + 11) in 2D
  * (gqd_apply_H and gqd_diag on 2D grids need it too).  The caller allocates it
  * (bytes from gqd_workspace_size) and passes it once; it must stay valid. */
 gqd_status gqd_workspace_size(const gqd_handle* h, const gqd_solver_opts* o, size_t* bytes);

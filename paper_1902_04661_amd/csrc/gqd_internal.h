@@ -179,7 +179,7 @@ constexpr int kLine2N[kNumLine2] = {64, 128, 256, 512};
 constexpr int kLineWaves = 4;                   // lines per block = waves per workgroup
 constexpr int kThreads2 = 64 * kLineWaves;
 // workspace per 2D item: kWork2Extra fixed slots, then the m + 1 basis vectors
-constexpr int kWork2Extra = 8;
+constexpr int kWork2Extra = 10;
 // reduction slots per workgroup: m + 1 complex dots plus a few reals
 constexpr int kPart2 = 2 * (kMaxRestart + 1) + 8;
 

@@ -271,11 +271,17 @@ __device__ __forceinline__ void block_map(bool row, int e, int& s, int& w, int& 
 }
 
 // Line operation request of the propagation machine.
+// The operand is x = scale * (src + src2 - sum_{i<K} coef_i basis_i) (src2 may be null,
+// coef in LDS); row and column blocks form it with the same operations, so both see
+// the same values, and row blocks store it to copy_dst.
 struct LineReq {
   const cplx* src;
-  cplx scale;        // src is multiplied by scale when `scaled`
+  const cplx* src2;
+  const cplx* basis;
+  int K;
+  cplx scale;        // applied when `scaled`
   bool scaled;
-  cplx* copy_dst;    // row blocks store the (scaled) source here (may be null)
+  cplx* copy_dst;    // may be null
   bool opH;          // true: H parts; false: A_d x along each axis
   cplx* out_r;       // rows:    A_2 A_2 x / (2 m_2) + V x   |  A_2 x
   cplx* out_c;       // columns: A_1 A_1 x / (2 m_1)         |  A_1 x
@@ -295,6 +301,8 @@ __device__ void line_op(const LineReq& q, const Ctx2& c, const K2Args& a, const 
       block_map<NL>(row, e, s, w, i);
       const int gi = line_gidx<NL>(row, s, l0 + w, i);
       cplx v = q.src[gi];
+      if (q.src2) v = cadd(v, q.src2[gi]);
+      for (int k = 0; k < q.K; ++k) v = csub(v, cmul(c.coef[k], q.basis[(size_t)k * E::VEC + gi]));
       if (q.scaled) v = cmul(q.scale, v);
       if (row && q.copy_dst) q.copy_dst[gi] = v;
       c.lines[(size_t)w * 4 * NL + s * NL + i] = v;
@@ -408,12 +416,17 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   cplx* X = wk;                   // solve output | phi
   cplx* B = wk + E::VEC;          // rhs          | mu
   cplx* HP = wk + 2 * E::VEC;     // H psi (trapezoid economy)
-  cplx* OR = wk + 3 * E::VEC;     // row part of the last H x | A_2 phi
-  cplx* OC = wk + 4 * E::VEC;     // column part              | A_1 phi
-  cplx* W = wk + 5 * E::VEC;      // unnormalised Arnoldi vector
+  // row and column parts of the last H x (or A_2 phi, A_1 phi), and a spare pair that
+  // the next line operation writes while the current one may still be read
+  cplx* OR = wk + 3 * E::VEC;
+  cplx* OC = wk + 4 * E::VEC;
+  cplx* ORs = wk + 8 * E::VEC;
+  cplx* OCs = wk + 9 * E::VEC;
+  cplx* W = wk + 5 * E::VEC;      // partly orthogonalised Arnoldi vector, residual
   cplx* AR = wk + 6 * E::VEC;     // A_2 mu
   cplx* AC = wk + 7 * E::VEC;     // A_1 mu
   cplx* basis = wk + kWork2Extra * E::VEC;
+  static_assert(kWork2Extra == 10, "workspace slots");
   GridSync sy{a.sync + 2 * item, a.sync + 2 * item + 1, 0u, G, a.spin_limit};
   double* part = a.part + (size_t)item * 2 * G * kPart2;
   int par = 0;
@@ -438,7 +451,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   int cc = adj ? a.gt.count - 1 : 0;
   double alpha = 0.0;
 
-  bool pending = false;
+  bool pending = false, swap_after = false;
   LineReq rq{};
   const cplx* bg = nullptr;
   cplx* xg = nullptr;
@@ -446,16 +459,19 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   int j = 0, iters = 0, after = k2Substep;
   int pc = k2Substep;
   if (a.mode == kM2ApplyH || a.mode == kM2Diag) {
-    rq = LineReq{psi, mk(1.0, 0.0), false, nullptr, a.mode == kM2ApplyH, OR, OC};
+    rq = LineReq{psi, nullptr, nullptr, 0, mk(1.0, 0.0), false, nullptr, a.mode == kM2ApplyH, ORs, OCs};
     pending = true;
+    swap_after = true;
     pc = a.mode == kM2ApplyH ? k2ApplyDone : k2DiagDone;
   } else if (a.mode == kM2Inner) {
     pc = k2Inner;
   }
 
-  auto request = [&](const cplx* src, bool h, cplx* outr, cplx* outc) {
-    rq = LineReq{src, mk(1.0, 0.0), false, nullptr, h, outr, outc};
+  // H x (or A_d x) of a global vector into the spare pair, which becomes current
+  auto request = [&](const cplx* src, bool h) {
+    rq = LineReq{src, nullptr, nullptr, 0, mk(1.0, 0.0), false, nullptr, h, ORs, OCs};
     pending = true;
+    swap_after = true;
   };
   auto gsum = [&](int K) -> bool {
     touched = false;
@@ -478,7 +494,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
     const double bnorm = sqrt(uniform_d(c.red[0]));
     if (!isfinite(bnorm)) bad = true;
     tolb = a.sc.tol * bnorm;
-    request(b, true, OR, OC);
+    request(b, true);
     pc = k2SolveGuess;
     return true;
   };
@@ -503,14 +519,17 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
     pc = k2Substep;
   };
 
-  // partial sums of <v_i, y> over this chunk, i < K, into slots 2i, 2i+1 (four basis
-  // vectors per sweep so that y is read once per four)
-  auto chunk_dots = [&](const cplx* y, int K) {
+  // partial sums of <v_i, y> over this chunk, i < K, into slots 2i, 2i+1, with
+  // y = y1 (+ y2); with norm_slot >= 0, |y|^2 into that slot (four basis vectors per
+  // sweep so that y is read once per four)
+  auto chunk_dots = [&](const cplx* y1, const cplx* y2, int K, int norm_slot) {
+    double nn = 0.0;
     for (int i0 = 0; i0 < K; i0 += 4) {
       const int nv = K - i0 < 4 ? K - i0 : 4;
       double sx[4] = {0.0, 0.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, 0.0, 0.0};
       for (long long e = e0 + threadIdx.x; e < e1; e += T) {
-        const cplx w = y[e];
+        const cplx w = y2 ? cadd(y1[e], y2[e]) : y1[e];
+        if (i0 == 0) nn += cabs2(w);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
           if (u < nv) {
@@ -526,18 +545,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
           put_partial(c, 2 * (i0 + u) + 1, sv[u]);
         }
     }
-  };
-  // W -= sum_i coef_i v_i over this chunk (i < K); |W|^2 into slot 0
-  auto chunk_update = [&](int K) {
-    double acc = 0.0;
-    for (long long e = e0 + threadIdx.x; e < e1; e += T) {
-      cplx w = W[e];
-      for (int i = 0; i < K; ++i) w = csub(w, cmul(c.coef[i], basis[(size_t)i * E::VEC + e]));
-      W[e] = w;
-      acc += cabs2(w);
-    }
-    put_partial(c, 0, acc);
-    touched = true;
+    if (norm_slot >= 0) put_partial(c, norm_slot, nn);
   };
 
   for (;;) {
@@ -549,6 +557,14 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
       }
       line_op<NL>(rq, c, a, im, g);
       if (rq.opH) ++napply;
+      if (swap_after) {
+        cplx* t = OR;
+        OR = ORs;
+        ORs = t;
+        t = OC;
+        OC = OCs;
+        OCs = t;
+      }
       pending = false;
       touched = false;
       if (!grid_barrier(sy, c.scal + 15)) {
@@ -565,7 +581,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         } else if (midp) {
           solve_begin(psi, X, alpha, k2MidpAfter);
         } else if (literal || !have_hpsi) {
-          request(psi, true, OR, OC);
+          request(psi, true);
           pc = k2TrapHpsi;
         } else {
           pc = k2TrapHpsi;
@@ -602,7 +618,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
       }
       case k2MidpAfter: {
         if (literal) {
-          request(X, true, OR, OC);
+          request(X, true);
           pc = k2MidpExplicit;
           break;
         }
@@ -622,7 +638,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         for (long long e = e0 + threadIdx.x; e < e1; e += T)
           xg[e] = csub(bg[e], cmul_is(cadd(OR[e], OC[e]), al));  // x0 = (1 - i al H) b
         touched = true;
-        request(xg, true, OR, OC);
+        request(xg, true);
         pc = k2SolveResid;
         break;
       }
@@ -651,46 +667,51 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         if (threadIdx.x == 0) c.g[0] = mk(beta, 0.0);
         // v_0 = r / beta: the H request scales the residual on the fly and row blocks
         // store the scaled values as the first basis vector
-        rq = LineReq{W, mk(1.0 / beta, 0.0), true, basis, true, OR, OC};
+        rq = LineReq{W, nullptr, nullptr, 0, mk(1.0 / beta, 0.0), true, basis, true, ORs, OCs};
         pending = true;
+        swap_after = true;
         j = 0;
         pc = k2SolveArnoldi;
         break;
       }
       case k2SolveArnoldi: {
         ++iters;
-        // w = H v_j into W with |w|^2, then h_i = <v_i, w> for i <= j: one reduction
-        {
-          double nn = 0.0;
-          for (long long e = e0 + threadIdx.x; e < e1; e += T) {
-            const cplx w = cadd(OR[e], OC[e]);
-            W[e] = w;
-            nn += cabs2(w);
-          }
-          put_partial(c, 2 * (j + 1), nn);
-          chunk_dots(W, j + 1);
-          if (!gsum(2 * (j + 1) + 1)) break;
-        }
+        // w = H v_j = OR + OC: h_i = <v_i, w> (i <= j) and |w|^2 in one reduction;
+        // |w'|^2 = |w|^2 - sum |h_i|^2 when the pass keeps at least half of |w|^2
+        chunk_dots(OR, OC, j + 1, 2 * (j + 1));
+        if (!gsum(2 * (j + 1) + 1)) break;
         const double w2 = uniform_d(c.red[2 * (j + 1)]);
         for (int i = threadIdx.x; i <= j; i += T) {
           c.hcol[i] = mk(c.red[2 * i], c.red[2 * i + 1]);
           c.coef[i] = c.hcol[i];
         }
         __syncthreads();
-        chunk_update(j + 1);
-        if (!gsum(1)) break;
-        double hn2 = uniform_d(c.red[0]);
-        if (hn2 < kReorthRatio * w2) {  // second pass
-          chunk_dots(W, j + 1);
-          if (!gsum(2 * (j + 1))) break;
+        double hn2 = w2;
+        for (int i = 0; i <= j; ++i) hn2 -= cabs2(c.coef[i]);
+        hn2 = uniform_d(hn2);
+        const cplx* base = OR;
+        const cplx* base2 = OC;
+        if (hn2 < kReorthRatio * w2) {
+          // second pass: W = w - sum h_i v_i, then c_i = <v_i, W> and |W|^2 in one
+          // reduction; the update by c is left to the next operand load
+          for (long long e = e0 + threadIdx.x; e < e1; e += T) {
+            cplx w = cadd(OR[e], OC[e]);
+            for (int i = 0; i <= j; ++i) w = csub(w, cmul(c.coef[i], basis[(size_t)i * E::VEC + e]));
+            W[e] = w;
+          }
+          chunk_dots(W, nullptr, j + 1, 2 * (j + 1));
+          touched = true;
+          if (!gsum(2 * (j + 1) + 1)) break;
+          double r2 = uniform_d(c.red[2 * (j + 1)]);
           for (int i = threadIdx.x; i <= j; i += T) {
             c.coef[i] = mk(c.red[2 * i], c.red[2 * i + 1]);
             c.hcol[i] = cadd(c.hcol[i], c.coef[i]);
           }
           __syncthreads();
-          chunk_update(j + 1);
-          if (!gsum(1)) break;
-          hn2 = uniform_d(c.red[0]);
+          for (int i = 0; i <= j; ++i) r2 -= cabs2(c.coef[i]);
+          hn2 = uniform_d(r2 > 0.0 ? r2 : 0.0);
+          base = W;
+          base2 = nullptr;
         }
         const double hn = sqrt(hn2);
         for (int i = threadIdx.x; i <= j; i += T) {
@@ -708,9 +729,11 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         if (!cv && hn != 0.0 && iters < a.sc.maxit && j + 1 < m) {
           // v_(j+1) = i sign(al) w' / |w'|, formed while the next H application loads it
           const double sc = (al >= 0.0 ? 1.0 : -1.0) / hn;
+          const int K = j + 1;
           ++j;
-          rq = LineReq{W, mk(0.0, sc), true, basis + (size_t)j * E::VEC, true, OR, OC};
+          rq = LineReq{base, base2, basis, K, mk(0.0, sc), true, basis + (size_t)j * E::VEC, true, ORs, OCs};
           pending = true;
+          swap_after = true;
           break;
         }
         const int k = j + 1;
@@ -724,7 +747,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         if (cv) {
           solve_end(true);
         } else {
-          request(xg, true, OR, OC);
+          request(xg, true);
           pc = k2SolveResid;
         }
         break;
@@ -733,11 +756,13 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         solve_begin(lam, B, -alpha, k2AdjAfterMu);
         break;
       case k2AdjAfterMu:
-        request(X, false, OR, OC);
+        request(X, false);
         pc = k2AdjAphi;
         break;
       case k2AdjAphi:
-        request(B, false, AR, AC);
+        rq = LineReq{B, nullptr, nullptr, 0, mk(1.0, 0.0), false, nullptr, false, AR, AC};
+        pending = true;
+        swap_after = false;
         pc = k2AdjAmu;
         break;
       case k2AdjAmu: {
