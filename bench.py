@@ -354,7 +354,9 @@ def main(argv=None):
         "two_dim": twod,
         "adjoint_2d": adjoint2d,
         "gmres": {"mean_iterations": iters / solves, "h_applies_per_step": applies / args.steps,
-                  "solves_per_step": solves / args.steps},
+                  "solves_per_step": solves / args.steps,
+                  "substeps_per_s": solves / (avg_kernel_s * args.steps),
+                  "h_applies_per_s": applies / (avg_kernel_s * args.steps)},
         "check": check,
     }
     print(json.dumps(line), flush=True)
