@@ -6,10 +6,11 @@ Workload.  The two-surface NaI-like adiabatic model on N = 2048 points of [3, 16
 implicit midpoint method to order 8 (125 substeps per step), step dt = 10 a.u. (the
 largest dt_k = 40 * 2^-k whose error at T = 4000 a.u. against the dt/8 order-8
 reference is <= 1e-10; see paper_1902_04661_amd.convergence), GMRES tolerance 1e-14.
-A batch of B wavepackets with seeded centres, momenta and coupling amplitudes
-(U[4.5, 6], U[-5, 5], U[0.1, 0.8]; numpy default_rng(0)) fills the GPU; one "step"
-advances every packet by dt in one kernel launch.  The same model with one packet is
-timed too (single_packet).
+That packet (q0 = 5, p0 = 0, width 0.12, coupling amplitude 0.4 at q = 7), the one the
+step-size sweep was run on, is replicated B times to fill the GPU (weak scaling by
+batch); one "step" advances every copy by dt in one kernel launch.  One packet alone is
+timed too (single_packet), and a seeded ragged batch of different packets and sizes
+(ragged_batch).
 
 Roofline: the propagation kernel against the HBM peak (8 TB/s) with algorithmic bytes
 32 (I^2 + 4I + 8) per grid point per substep for a solve of I Arnoldi iterations
@@ -43,11 +44,11 @@ TOL = 1e-14
 # for a 1 GiB device copy (FETCH_SIZE 0.5x, WRITE_SIZE 1.0x of the true bytes).  Valid only
 # for the device sources it was taken on: reported as null once they change.
 TRAFFIC = {
-    "sources_sha256": "45d72ea929937aa1c59bcca6c5b608584f20d0ac2d1c3582faa2166a64e588ac",
-    "fetch_kib": 148926835.5625, "fetch_scale": 2.0,
-    "write_kib": 59426898.0, "write_scale": 1.0,
-    "alg_bytes_same_launch": 372962033664.0,
-    "summary": "profiles/k_run_2048_sz8_batch1024.md",
+    "sources_sha256": "5e25e60e427e0e0e0ab02e85f2b42db3132102e202ddbb9889a6fa041f9ef276",
+    "fetch_kib": 137572511.25, "fetch_scale": 2.0,
+    "write_kib": 56994185.625, "write_scale": 1.0,
+    "alg_bytes_same_launch": 331987550208.0,
+    "summary": "profiles/k_run_2048_sz8_x1024.md",
 }
 DEVICE_SOURCES = ["gqd_kernels.hip", "gqd_device.hpp", "gqd_internal.h"]
 
@@ -236,7 +237,7 @@ def main(argv=None):
     opts = gqd.SolverOpts(tol=TOL, restart=32)
 
     # ---------------------------------------------------------------- batched run
-    items = inputs.ragged_batch(args.batch, seed=0, fixed_n=N)
+    items = [inputs.nai_like_item(N)] * args.batch
     prop = gqd.from_items(items, device=dev)
     psi0 = prop.pack([it.psi0 for it in items])
     psi = psi0.clone()
@@ -320,7 +321,7 @@ def main(argv=None):
         cpu = cpu_leg()
         print(f"[bench] cpu oracle: {cpu['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
 
-    traffic, traffic_ratio = measured_traffic() if args.batch == 1024 else (None, None)
+    traffic, traffic_ratio = measured_traffic() if args.batch == 1024 and not args.no_autotune else (None, None)
     line = {
         "metric": METRIC,
         "value": value,
@@ -334,8 +335,9 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"nai2048_sz8_midpoint_dt10_batch{args.batch}",
-                   "model": "two-surface NaI-like adiabatic model, N=2048 on [3,16) bohr",
+        "config": {"workload": f"nai2048_sz8_midpoint_dt10_x{args.batch}",
+                   "model": "two-surface NaI-like adiabatic model, N=2048 on [3,16) bohr; "
+                            "packet q0=5 p0=0 w=0.12 on surface 1, replicated",
                    "batch": args.batch, "n": N, "method": "implicit midpoint", "scheme": "suzuki",
                    "order": ORDER, "dt": DT_STAR, "gmres_tol": TOL, "restart": 32,
                    "substeps_per_step": 125, "parallelism": "one workgroup per wavepacket",
