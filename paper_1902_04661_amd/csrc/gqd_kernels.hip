@@ -52,6 +52,15 @@ struct Eng {
     double inv2m;
   };
 
+  // LDS slot of transform element i in a swizzled buffer: the 8-element block index
+  // (bits 3-5) is XORed into the low three bits.  Two writes of the transform give each
+  // thread a run of R consecutive elements (the register-held first pass and the fused
+  // k-space pass); unswizzled, eight lanes of such a 16-byte store hit the same four
+  // banks.  Only those two outputs are swizzled, and only the passes that read them
+  // apply the map; where a butterfly's inputs are a multiple of 64 elements apart the
+  // XOR term is the same for all of them and is computed once.
+  static __device__ __forceinline__ int swz(int i) { return i ^ ((i >> 3) & 7); }
+
   // owned point r of this lane; lane_tid() keeps address arithmetic local to its use
   static __device__ __forceinline__ int pt(int r) { return lane_tid() + r * T; }
 
@@ -221,7 +230,7 @@ struct Eng {
   // Butterfly j (< N/R) of surface s reads x[j + r N/R], twiddles by w_{Ns R}^{r k}
   // (k = j mod Ns), applies the radix-R DFT and writes y[(j/Ns) Ns R + k + r Ns].
   // `next` issues the next pass's twiddle loads before the closing barrier.
-  template <int R, int Ns, int S, class Next>
+  template <int R, int Ns, int S, bool SWIN = false, class Next>
   static __device__ __forceinline__ void pass(const GQD_L cplx* src, GQD_L cplx* dst, const TwS<R, Ns>& tw,
                                               Next&& next) {
     constexpr int NB = 2 * N / R;
@@ -233,8 +242,17 @@ struct Eng {
     for (int q = 0; q < PER; ++q) {
       const int b = tid + q * T;
       const int s = b / (N / R), j = b % (N / R);
+      if constexpr (SWIN && (N / R) % 64 == 0) {
+        const int i0 = s * N + swz(j);  // inputs 64k apart share the XOR term
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[q][r] = src[s * N + j + r * (N / R)];
+        for (int r = 0; r < R; ++r) x[q][r] = src[i0 + r * (N / R)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = s * N + j + r * (N / R);
+          x[q][r] = src[SWIN ? swz(i) : i];
+        }
+      }
     }
     if constexpr (!kPP) __syncthreads();  // in place: all reads before any write
     tid = lane_tid();
@@ -291,7 +309,7 @@ struct Eng {
       }
       DFT<RF, +1>::run(x[q]);
 #pragma unroll
-      for (int r = 0; r < RF; ++r) dst[s * N + j * RF + r] = x[q][r];
+      for (int r = 0; r < RF; ++r) dst[s * N + swz(j * RF + r)] = x[q][r];
     }
     next();
     __syncthreads();
@@ -311,7 +329,7 @@ struct Eng {
       for (int r = 0; r < R0; ++r) y[r] = x.v[s][r];
       DFT<R0, -1>::run(y);
 #pragma unroll
-      for (int r = 0; r < R0; ++r) b0[s * N + lane_tid() * R0 + r] = y[r];
+      for (int r = 0; r < R0; ++r) b0[s * N + swz(lane_tid() * R0 + r)] = y[r];
     }
     tw_load<R1, R0, 0>(t0, opaque(c.tw));
     __syncthreads();
@@ -319,18 +337,18 @@ struct Eng {
     if constexpr (R3 == 1) {
       TwS<RF, N / RF> tf;
       TwS<R1, R2> t2;
-      pass<R1, R0, -1>(b0, b1, t0, [&] { tw_load<RF, N / RF, 1>(tf, opaque(c.tw)); });
+      pass<R1, R0, -1, true>(b0, b1, t0, [&] { tw_load<RF, N / RF, 1>(tf, opaque(c.tw)); });
       fused_kspace(b1, b0, tf, c, [&] { tw_load<R1, R2, 2>(t2, opaque(c.tw)); });
-      pass<R1, R2, +1>(b0, b1, t2, [&] { tw_load<R0, T, PL>(tl, opaque(c.tw)); });
+      pass<R1, R2, +1, true>(b0, b1, t2, [&] { tw_load<R0, T, PL>(tl, opaque(c.tw)); });
     } else {
       TwS<R2, R0 * R1> t1;
       TwS<RF, N / RF> tf;
       TwS<R2, R3> t3;
       TwS<R1, R3 * R2> t4;
-      pass<R1, R0, -1>(b0, b1, t0, [&] { tw_load<R2, R0 * R1, 1>(t1, opaque(c.tw)); });
+      pass<R1, R0, -1, true>(b0, b1, t0, [&] { tw_load<R2, R0 * R1, 1>(t1, opaque(c.tw)); });
       pass<R2, R0 * R1, -1>(b1, b0, t1, [&] { tw_load<RF, N / RF, 2>(tf, opaque(c.tw)); });
       fused_kspace(b0, b1, tf, c, [&] { tw_load<R2, R3, 3>(t3, opaque(c.tw)); });
-      pass<R2, R3, +1>(b1, b0, t3, [&] { tw_load<R1, R3 * R2, 4>(t4, opaque(c.tw)); });
+      pass<R2, R3, +1, true>(b1, b0, t3, [&] { tw_load<R1, R3 * R2, 4>(t4, opaque(c.tw)); });
       pass<R1, R3 * R2, +1>(b0, b1, t4, [&] { tw_load<R0, T, PL>(tl, opaque(c.tw)); });
     }
     // last inverse pass: radix R0, Ns = T, butterfly j = thread -> owned points
