@@ -164,7 +164,8 @@ inline size_t lds_bytes(int plan, int m) {
   const int N = kPlans[plan].N;
   const int W = plan_threads(plan) / 64;
   const size_t fft = kPlans[plan].two_buf ? 4 * (size_t)N : 2 * (size_t)N;
-  const size_t c = fft + (size_t)W * (m + 1) + 2 * (m + 1) + 2 * (size_t)m + (size_t)m * (m + 1) / 2;
+  // fft, part [W][m+1], hcol [m+1], g [m+1], sn [m], y [m+1], R [m(m+1)/2]; cs [m], scal [16]
+  const size_t c = fft + (size_t)W * (m + 1) + 3 * (size_t)(m + 1) + (size_t)m + (size_t)m * (m + 1) / 2;
   return c * 16 + (size_t)m * 8 + 16 * 8;
 }
 

@@ -40,7 +40,7 @@ struct Eng {
     GQD_L cplx* hcol;  // [kmax]
     GQD_L cplx* g;     // [kmax]
     GQD_L cplx* sn;    // [m]
-    GQD_L cplx* y;     // [m]
+    GQD_L cplx* y;     // [m + 1]
     GQD_L cplx* R;     // [m(m+1)/2], column j at j(j+1)/2
     GQD_L double* cs;     // [m]
     GQD_L double* scal;   // [16]
@@ -74,7 +74,7 @@ struct Eng {
     c.g = c.hcol + kmax;
     c.sn = c.g + kmax;
     c.y = c.sn + m;
-    c.R = c.y + m;
+    c.R = c.y + (m + 1);
     c.cs = (GQD_L double*)(c.R + (m * (m + 1)) / 2);
     c.scal = c.cs + m;
     c.V = a.V + im.voff;
@@ -792,15 +792,21 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         // Column j of the Hessenberg matrix of X = 1 + i al H is delta_ij + i al h_ij,
         // and v_(j+1) = i sign(al) w'/|w'| makes its subdiagonal |al| |w'| real.
         ++iters;
+        // |w'|^2 = |w|^2 - sum |h_i|^2 when the pass keeps at least half of |w|^2 (a
+        // few ulp there); a second pass returns its own |w'|^2 from the same reduction
         E::block_dots(basis, y, j + 1, c, c.hcol, true);
         const double w2 = uniform_d(c.hcol[j + 1].x);
+        double hn2 = w2;
+        for (int i = 0; i <= j; ++i) hn2 -= cabs2(c.hcol[i]);
+        hn2 = uniform_d(hn2);
         E::block_axpy(basis, c.hcol, j + 1, y);
-        double hn2 = E::block_sum1(E::norm2(y), c);
         if (hn2 < kReorthRatio * w2) {
-          E::block_dots(basis, y, j + 1, c, c.y);
+          E::block_dots(basis, y, j + 1, c, c.y, true);
+          double r2 = uniform_d(c.y[j + 1].x);
+          for (int i = 0; i <= j; ++i) r2 -= cabs2(c.y[i]);
+          hn2 = uniform_d(r2 > 0.0 ? r2 : 0.0);
           E::block_axpy(basis, c.y, j + 1, y);
           for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);
-          hn2 = E::block_sum1(E::norm2(y), c);  // its barriers order the hcol update
         }
         const double hn = sqrt(hn2);
         for (int i = threadIdx.x; i <= j; i += T) {
@@ -833,13 +839,19 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           OV x;
           E::load(x, xg);
 #pragma unroll 1
-          for (int i = 0; i < k; ++i) {
-            const cplx* Vi = basis + (size_t)i * E::VEC;
-            const cplx yi = c.y[i];
+          for (int i = 0; i < k; i += E::GSV) {
+            const bool two = E::GSV == 2 && i + 1 < k;
+            const GQD_G cplx* Va = opaque(basis + (size_t)i * E::VEC);
+            const GQD_G cplx* Vb = opaque(basis + (size_t)(two ? i + 1 : i) * E::VEC);
+            const cplx ya = c.y[i];
+            const cplx yb = two ? c.y[i + 1] : mk(0.0, 0.0);
 #pragma unroll
             for (int s = 0; s < 2; ++s)
 #pragma unroll
-              for (int r = 0; r < R0; ++r) x.v[s][r] = cadd(x.v[s][r], cmul(yi, Vi[s * N + E::pt(r)]));
+              for (int r = 0; r < R0; ++r) {
+                x.v[s][r] = cadd(x.v[s][r], cmul(ya, Va[s * N + E::pt(r)]));
+                if constexpr (E::GSV == 2) x.v[s][r] = cadd(x.v[s][r], cmul(yb, Vb[s * N + E::pt(r)]));
+              }
           }
           E::store(x, xg);
         }
