@@ -125,16 +125,6 @@ gqd_status run2d(gqd_handle* h, K2Args a, hipStream_t stream) {
   const int per_launch = resident / G;
   a.G = G;
   a.work_stride = (long long)(kWork2Extra + a.sc.m + 1) * vec;
-  a.sync = h->d_sync;
-  a.part = h->d_part;
-  a.spin_limit = kSpinLimit;
-  a.tw = h->d_tw2;
-  a.V = h->V;
-  a.F = h->F;
-  a.inv2m0 = 1.0 / (2.0 * h->mass2[0]);
-  a.inv2m1 = 1.0 / (2.0 * h->mass2[1]);
-  a.mass0 = h->mass2[0];
-  a.mass1 = h->mass2[1];
   double* out0 = a.out;
   for (int base = 0; base < h->batch; base += per_launch) {
     const int cnt = (h->batch - base < per_launch) ? h->batch - base : per_launch;
@@ -152,6 +142,16 @@ gqd_status run2d(gqd_handle* h, K2Args a, hipStream_t stream) {
 K2Args base_args2(const gqd_handle* h) {
   K2Args a;
   std::memset(&a, 0, sizeof(a));
+  a.V = h->V;
+  a.F = h->F;
+  a.tw = h->d_tw2;
+  a.inv2m0 = 1.0 / (2.0 * h->mass2[0]);
+  a.inv2m1 = 1.0 / (2.0 * h->mass2[1]);
+  a.mass0 = h->mass2[0];
+  a.mass1 = h->mass2[1];
+  a.sync = h->d_sync;
+  a.part = h->d_part;
+  a.spin_limit = kSpinLimit;
   return a;
 }
 
