@@ -167,7 +167,7 @@ gqd_status ensure_streams(gqd_handle* h) {
 }
 
 // Launch `fn` once per non-empty size class.  Several classes run concurrently on
-// side streams forked from and joined back into the caller's stream.
+// side streams forked from and joined back into the caller's stream, largest first.
 template <class Fn>
 gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
   int active = 0;
@@ -185,7 +185,9 @@ gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
   gqd_status st = ensure_streams(h);
   if (st != GQD_OK) return st;
   GQD_HIP(hipEventRecord(h->ev_fork, stream));
-  for (int c = 0; c < kNumClasses; ++c) {
+  // largest grids first: they carry most of the work, and side streams that share a
+  // hardware queue run their kernels one after the other
+  for (int c = kNumClasses - 1; c >= 0; --c) {
     if (h->class_lists[c].empty()) continue;
     GQD_HIP(hipStreamWaitEvent(h->side[c], h->ev_fork, 0));
     a.list = h->d_lists[c];
