@@ -44,9 +44,9 @@ TOL = 1e-14
 # for a 1 GiB device copy (FETCH_SIZE 0.5x, WRITE_SIZE 1.0x of the true bytes).  Valid only
 # for the device sources it was taken on: reported as null once they change.
 TRAFFIC = {
-    "sources_sha256": "5e25e60e427e0e0e0ab02e85f2b42db3132102e202ddbb9889a6fa041f9ef276",
-    "fetch_kib": 137572511.25, "fetch_scale": 2.0,
-    "write_kib": 56994185.625, "write_scale": 1.0,
+    "sources_sha256": "48cc0cb94a4a37c258e7ff7afc19d6cee248920c9e7ee8de4139feadddca394f",
+    "fetch_kib": 145068388.875, "fetch_scale": 2.0,
+    "write_kib": 57000668.375, "write_scale": 1.0,
     "alg_bytes_same_launch": 331987550208.0,
     "summary": "profiles/k_run_2048_sz8_x1024.md",
 }
