@@ -216,8 +216,9 @@ def main(argv=None):
                     help="only copy MIB MiB device-to-device once (HBM counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs each batch on a single MI355X "
-              "(multi-GPU sharding is described in the design notes, not run).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs each batch on a single MI355X; "
+              "items are independent, and sharding a batch across GPUs is not implemented.",
+              file=sys.stderr)
         return 2
 
     import numpy as np

@@ -243,3 +243,14 @@ def test_autotune_keeps_results(gqd):
     for it, out in zip(items, prop.unpack(psi)):
         ref = O.propagate(O.model_from_item(it), it.psi0, O.MIDP, O.SUZUKI, 4, 10.0, 1, O.SolverOpts(**opts))
         assert rel(out, ref) <= 1e-12
+
+
+def test_restart_beyond_lds_is_rejected(gqd):
+    # N = 2048 with two LDS transform buffers leaves room for at most 52 Krylov vectors
+    it = I.nai_like_item(2048)
+    prop = gqd.from_items([it])
+    psi = prop.pack([it.psi0])
+    with pytest.raises(gqd.GqdError) as err:
+        prop.propagate(psi, "midp", "suzuki", 2, 10.0, 1, gqd.SolverOpts(restart=64))
+    assert err.value.code == -5 and "LDS" in str(err.value)
+    prop.propagate(psi, "midp", "suzuki", 2, 10.0, 1, gqd.SolverOpts(restart=52))
