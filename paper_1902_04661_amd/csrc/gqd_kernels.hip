@@ -412,16 +412,16 @@ struct Eng {
     }
   }
 
-  // pre = (-i F chi) / (2m) + V x written to dst (global), x read from xs;
+  // pre = (-i F chi) / (2m) + (V - shift) x written to dst (global), x read from xs;
   // the outer A's coupling and the potential, formed before the second transform.
   template <class P, class Q>
-  static __device__ __forceinline__ void make_pre(const OV& chi, P xs, Q dst, const Ctx& c) {
+  static __device__ __forceinline__ void make_pre(const OV& chi, P xs, Q dst, double shift, const Ctx& c) {
     const GQD_G double* F = opaque(c.F);
     const GQD_G double* V = opaque(c.V);
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
       const double f = F[pt(r)];
-      const double v0 = V[pt(r)], v1 = V[N + pt(r)];
+      const double v0 = V[pt(r)] - shift, v1 = V[N + pt(r)] - shift;
       const cplx x0 = xs[pt(r)], x1 = xs[N + pt(r)];
       const cplx p0 = cadd(cscale(cmul_is(chi.v[1][r], -f), c.inv2m), cscale(x0, v0));
       const cplx p1 = cadd(cscale(cmul_is(chi.v[0][r], f), c.inv2m), cscale(x1, v1));
@@ -440,13 +440,13 @@ struct Eng {
       y.v[1][r] = cadd(y.v[1][r], cmul_is(x.v[0][r], f));
     }
   }
-  static __device__ __forceinline__ void make_pre(const OV& chi, OV& xp, const Ctx& c) {
+  static __device__ __forceinline__ void make_pre(const OV& chi, OV& xp, double shift, const Ctx& c) {
     const GQD_G double* F = opaque(c.F);
     const GQD_G double* V = opaque(c.V);
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
       const double f = F[pt(r)];
-      const double v0 = V[pt(r)], v1 = V[N + pt(r)];
+      const double v0 = V[pt(r)] - shift, v1 = V[N + pt(r)] - shift;
       const cplx p0 = cadd(cscale(cmul_is(chi.v[1][r], -f), c.inv2m), cscale(xp.v[0][r], v0));
       const cplx p1 = cadd(cscale(cmul_is(chi.v[0][r], f), c.inv2m), cscale(xp.v[1][r], v1));
       xp.v[0][r] = p0;
@@ -498,7 +498,7 @@ enum Pc {
   kSubstep,       // start the next substep (or finish)
   kSolveGuess,    // have H b: form x0 = (1 - i al H) b, ask for H x0
   kSolveResid,    // have H x: true residual, restart or finish the solve
-  kSolveArnoldi,  // have H v_j: Arnoldi step j
+  kSolveArnoldi,  // have (H - s) v_j: Arnoldi step j
   kMidpAfter,     // midpoint: x solved
   kMidpExplicit,  // midpoint, literal: have H x
   kTrapHpsi,      // trapezoid: have H psi
@@ -520,7 +520,8 @@ enum Pc {
 //   midpoint (Eq. 19):  x = (1 + i alpha H)^-1 psi;  psi' = (1 - i alpha H) x, or 2x - psi
 //   trapezoid (Eq. 18): b = (1 - i alpha H) psi;     psi' = (1 + i alpha H)^-1 b
 // Each inverse is restarted GMRES(m) from x0 = (1 - i alpha H) b, with the Arnoldi
-// basis built from H (classical Gram-Schmidt, a second pass on cancellation) and
+// basis built from H - s, s a real shift near the Rayleigh quotient of the first basis
+// vector (classical Gram-Schmidt, a second pass on cancellation) and
 // Givens rotations on the Hessenberg matrix of 1 + i alpha H; it stops when the
 // residual estimate is <= tol ||b||.
 //
@@ -565,10 +566,15 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
   int cc = adj ? a.gt.count - 1 : 0;
   double alpha = 0.0;
 
-  // operator request
+  // operator request: H - opshift applied to opsrc (opshift = 0 outside Arnoldi)
   bool pending = false, opH = false;
   int half = 0;
   const cplx* opsrc = nullptr;
+  double opshift = 0.0;
+  // Arnoldi runs on H - s, s the Rayleigh quotient of the first basis vector of the
+  // previous solve of the same kind (sig0: psi or phi, sig1: the adjoint's mu)
+  double sig0 = 0.0, sig1 = 0.0;
+  bool kind_mu = false;
   // solve state
   const cplx* bg = nullptr;
   cplx* xg = nullptr;
@@ -578,10 +584,11 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
   int pc = kSubstep;
   OV y, keep;
 
-  auto request = [&](const cplx* src, bool h) {
+  auto request = [&](const cplx* src, bool h, double shift = 0.0) {
     pending = true;
     opsrc = src;
     opH = h;
+    opshift = shift;
     half = 0;
   };
   // start a solve of (1 + i al H) x = b: ||b||, then ask for H b
@@ -590,6 +597,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
     xg = x;
     al = alv;
     after = ret;
+    kind_mu = ret == kAdjAfterMu;
     iters = 0;
     OV t;
     E::load(t, b);
@@ -637,10 +645,10 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
       if (half == 0) {
         if constexpr (E::kPP) {
           E::couple(y, keep, c);
-          if (opH) E::make_pre(y, keep, c);
+          if (opH) E::make_pre(y, keep, opshift, c);
         } else {
           E::couple(y, opaque(opsrc), c);
-          if (opH) E::make_pre(y, opaque(opsrc), opaque(CHI), c);
+          if (opH) E::make_pre(y, opaque(opsrc), opaque(CHI), opshift, c);
         }
         if (opH) {
           half = 1;
@@ -781,21 +789,28 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         if (threadIdx.x == 0) c.g[0] = mk(beta, 0.0);
         // (the next block reduction's barrier orders this write before any read)
         j = 0;
-        request(basis, true);
+        request(basis, true, kind_mu ? sig1 : sig0);
         pc = kSolveArnoldi;
         break;
       }
       case kSolveArnoldi: {
-        // Arnoldi on H (the Krylov space of 1 + i al H is that of H): y = H v_j is
-        // orthogonalised against v_0..v_j by classical Gram-Schmidt, with a second pass
-        // only when the first cancels all but kReorthRatio of |w|^2.
-        // Column j of the Hessenberg matrix of X = 1 + i al H is delta_ij + i al h_ij,
-        // and v_(j+1) = i sign(al) w'/|w'| makes its subdiagonal |al| |w'| real.
+        // Arnoldi on H - s (the Krylov space of 1 + i al H is that of H - s for any real
+        // shift s): y = (H - s) v_j is orthogonalised against v_0..v_j by classical
+        // Gram-Schmidt, with a second pass only when the first cancels all but
+        // kReorthRatio of |w|^2.  With s near the Rayleigh quotient of v_0 that
+        // cancellation is small, and the second pass is rarely needed.
+        // Column j of the Hessenberg matrix of X = 1 + i al H is delta_ij + i al (h_ij +
+        // s delta_ij), and v_(j+1) = i sign(al) w'/|w'| makes its subdiagonal |al| |w'| real.
         ++iters;
+        const double sh = opshift;
         // |w'|^2 = |w|^2 - sum |h_i|^2 when the pass keeps at least half of |w|^2 (a
         // few ulp there); a second pass returns its own |w'|^2 from the same reduction
         E::block_dots(basis, y, j + 1, c, c.hcol, true);
         const double w2 = uniform_d(c.hcol[j + 1].x);
+        if (j == 0) {  // <v_0|H v_0>, the shift of the following columns and solves
+          const double rq = uniform_d(c.hcol[0].x) + sh;
+          if (kind_mu) sig1 = rq; else sig0 = rq;
+        }
         double hn2 = w2;
         for (int i = 0; i <= j; ++i) hn2 -= cabs2(c.hcol[i]);
         hn2 = uniform_d(hn2);
@@ -810,8 +825,12 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         }
         const double hn = sqrt(hn2);
         for (int i = threadIdx.x; i <= j; i += T) {
-          const cplx hx = cmul_is(c.hcol[i], al);  // i al h_ij
-          c.hcol[i] = (i == j) ? mk(1.0 + hx.x, hx.y) : hx;
+          if (i == j) {
+            const cplx hx = cmul_is(mk(c.hcol[i].x + sh, c.hcol[i].y), al);  // i al (h_jj + s)
+            c.hcol[i] = mk(1.0 + hx.x, hx.y);
+          } else {
+            c.hcol[i] = cmul_is(c.hcol[i], al);  // i al h_ij
+          }
         }
         __syncthreads();
         E::givens_update(j, fabs(al) * hn, c);
@@ -829,7 +848,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
             for (int r = 0; r < R0; ++r) y.v[s][r] = cmul_is(y.v[s][r], sc);
           ++j;
           E::store(y, basis + (size_t)j * E::VEC);
-          request(basis + (size_t)j * E::VEC, true);
+          request(basis + (size_t)j * E::VEC, true, kind_mu ? sig1 : sig0);
           break;
         }
         // cycle ends: x += V y over the k = j + 1 basis vectors

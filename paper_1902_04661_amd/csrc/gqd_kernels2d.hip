@@ -283,8 +283,9 @@ struct LineReq {
   bool scaled;
   cplx* copy_dst;    // may be null
   bool opH;          // true: H parts; false: A_d x along each axis
-  cplx* out_r;       // rows:    A_2 A_2 x / (2 m_2) + V x   |  A_2 x
-  cplx* out_c;       // columns: A_1 A_1 x / (2 m_1)         |  A_1 x
+  cplx* out_r;       // rows:    A_2 A_2 x / (2 m_2) + (V - shift) x   |  A_2 x
+  cplx* out_c;       // columns: A_1 A_1 x / (2 m_1)                   |  A_1 x
+  double shift = 0.0;  // H - shift (Arnoldi only)
 };
 
 template <int NL>
@@ -332,7 +333,7 @@ __device__ void line_op(const LineReq& q, const Ctx2& c, const K2Args& a, const 
 #pragma unroll
         for (int r = 0; r < E::P; ++r) {
           y[s][r] = cscale(z[s][r], inv2m);
-          if (row) y[s][r] = cadd(y[s][r], cscale(x[s][r], V[line_gidx<NL>(true, s, ln, lane + 64 * r)]));
+          if (row) y[s][r] = cadd(y[s][r], cscale(x[s][r], V[line_gidx<NL>(true, s, ln, lane + 64 * r)] - q.shift));
         }
     }
     GQD_L cplx* outl = c.lines + (size_t)wave * 4 * NL;
@@ -393,8 +394,9 @@ __device__ __forceinline__ double substep_tau2(int cc, const GammaTab& gt) {
 //   psi <- 2 phi - psi, lambda <- 2 mu - lambda and, per axis d,
 //   gF_d += -(2 alpha / m_d) Re[conj(mu1)(A_d phi)2 - conj(mu2)(A_d phi)1
 //                                + conj(A_d mu)1 phi2 - conj(A_d mu)2 phi1].
-// GMRES(m) from x0 = (1 - i al H) b with an Arnoldi basis of H (classical
-// Gram-Schmidt, a second pass when the first removes all but kReorthRatio of |w|^2) and
+// GMRES(m) from x0 = (1 - i al H) b with an Arnoldi basis of H - s, s a real shift near
+// the Rayleigh quotient of v_0 (classical Gram-Schmidt, a second pass when the first
+// removes all but kReorthRatio of |w|^2) and
 // Givens rotations on the Hessenberg matrix of 1 + i al H; stop at |g_(j+1)| <= tol |b|.
 template <int NL>
 __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
@@ -458,6 +460,10 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   double al = 0.0, tolb = 0.0;
   int j = 0, iters = 0, after = k2Substep;
   int pc = k2Substep;
+  // Arnoldi runs on H - s, s the Rayleigh quotient of the first basis vector of the
+  // previous solve of the same kind (sig0: psi or phi, sig1: the adjoint's mu)
+  double sig0 = 0.0, sig1 = 0.0;
+  bool kind_mu = false;
   if (a.mode == kM2ApplyH || a.mode == kM2Diag) {
     rq = LineReq{psi, nullptr, nullptr, 0, mk(1.0, 0.0), false, nullptr, a.mode == kM2ApplyH, ORs, OCs};
     pending = true;
@@ -486,6 +492,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
     xg = x;
     al = alv;
     after = ret;
+    kind_mu = ret == k2AdjAfterMu;
     iters = 0;
     double acc = 0.0;
     for (long long e = e0 + threadIdx.x; e < e1; e += T) acc += cabs2(b[e]);
@@ -667,7 +674,8 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         if (threadIdx.x == 0) c.g[0] = mk(beta, 0.0);
         // v_0 = r / beta: the H request scales the residual on the fly and row blocks
         // store the scaled values as the first basis vector
-        rq = LineReq{W, nullptr, nullptr, 0, mk(1.0 / beta, 0.0), true, basis, true, ORs, OCs};
+        rq = LineReq{W, nullptr, nullptr, 0, mk(1.0 / beta, 0.0), true, basis, true, ORs, OCs,
+                     kind_mu ? sig1 : sig0};
         pending = true;
         swap_after = true;
         j = 0;
@@ -676,11 +684,18 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
       }
       case k2SolveArnoldi: {
         ++iters;
-        // w = H v_j = OR + OC: h_i = <v_i, w> (i <= j) and |w|^2 in one reduction;
-        // |w'|^2 = |w|^2 - sum |h_i|^2 when the pass keeps at least half of |w|^2
+        // w = (H - s) v_j = OR + OC: h_i = <v_i, w> (i <= j) and |w|^2 in one reduction;
+        // |w'|^2 = |w|^2 - sum |h_i|^2 when the pass keeps at least half of |w|^2.  The
+        // shift s (any real s spans the same Krylov space) shrinks |w| and with it the
+        // cancellation, so the second pass is rarely needed.
+        const double sh = rq.shift;
         chunk_dots(OR, OC, j + 1, 2 * (j + 1));
         if (!gsum(2 * (j + 1) + 1)) break;
         const double w2 = uniform_d(c.red[2 * (j + 1)]);
+        if (j == 0) {  // <v_0|H v_0>, the shift of the following columns and solves
+          const double rq0 = uniform_d(c.red[0]) + sh;
+          if (kind_mu) sig1 = rq0; else sig0 = rq0;
+        }
         for (int i = threadIdx.x; i <= j; i += T) {
           c.hcol[i] = mk(c.red[2 * i], c.red[2 * i + 1]);
           c.coef[i] = c.hcol[i];
@@ -715,8 +730,12 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         }
         const double hn = sqrt(hn2);
         for (int i = threadIdx.x; i <= j; i += T) {
-          const cplx hx = cmul_is(c.hcol[i], al);  // i al h_ij
-          c.hcol[i] = (i == j) ? mk(1.0 + hx.x, hx.y) : hx;
+          if (i == j) {
+            const cplx hx = cmul_is(mk(c.hcol[i].x + sh, c.hcol[i].y), al);  // i al (h_jj + s)
+            c.hcol[i] = mk(1.0 + hx.x, hx.y);
+          } else {
+            c.hcol[i] = cmul_is(c.hcol[i], al);  // i al h_ij
+          }
         }
         __syncthreads();
         gm_givens(j, fabs(al) * hn, c);
@@ -731,7 +750,8 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
           const double sc = (al >= 0.0 ? 1.0 : -1.0) / hn;
           const int K = j + 1;
           ++j;
-          rq = LineReq{base, base2, basis, K, mk(0.0, sc), true, basis + (size_t)j * E::VEC, true, ORs, OCs};
+          rq = LineReq{base, base2, basis, K, mk(0.0, sc), true, basis + (size_t)j * E::VEC, true, ORs, OCs,
+                       kind_mu ? sig1 : sig0};
           pending = true;
           swap_after = true;
           break;
