@@ -44,9 +44,9 @@ TOL = 1e-14
 # for a 1 GiB device copy (FETCH_SIZE 0.5x, WRITE_SIZE 1.0x of the true bytes).  Valid only
 # for the device sources it was taken on: reported as null once they change.
 TRAFFIC = {
-    "sources_sha256": "48cc0cb94a4a37c258e7ff7afc19d6cee248920c9e7ee8de4139feadddca394f",
-    "fetch_kib": 145068388.875, "fetch_scale": 2.0,
-    "write_kib": 57000668.375, "write_scale": 1.0,
+    "sources_sha256": "9522191fd77bb469685ca5afb56c85e1893fd81ed3a8d72e44bfded9e051e007",
+    "fetch_kib": 143522870.1875, "fetch_scale": 2.0,
+    "write_kib": 57001163.375, "write_scale": 1.0,
     "alg_bytes_same_launch": 331987550208.0,
     "summary": "profiles/k_run_2048_sz8_x1024.md",
 }
@@ -347,7 +347,7 @@ def main(argv=None):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (launch from t = 0, rocprofv3 --pmc)",
                      "traffic_over_alg_bytes": traffic_ratio,
-                     "kernel": "k_run<2048> (propagate)",
+                     "kernel": "k_run<7> (propagate, N = 2048 plan 4-8-8-8)",
                      "alg_bytes_per_launch": bytes_total / args.steps,
                      "avg_launch_ms": avg_kernel_s * 1e3},
         "cpu_baseline": cpu,
