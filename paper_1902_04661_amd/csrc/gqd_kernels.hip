@@ -822,6 +822,10 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           hn2 = uniform_d(r2 > 0.0 ? r2 : 0.0);
           E::block_axpy(basis, c.y, j + 1, y);
           for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);
+        } else {
+          // every wave has read h (above and in block_axpy) before the first wave
+          // overwrites it with the column of X below
+          __syncthreads();
         }
         const double hn = sqrt(hn2);
         for (int i = threadIdx.x; i <= j; i += T) {
