@@ -23,11 +23,15 @@ struct Eng {
   // operator input kept in registers; in-place classes: one buffer, the input re-read
   // and the partial H result parked in the workspace
   static constexpr bool kPP = kPlans[PLAN].two_buf;
-  // waves per SIMD the register allocation must leave room for: in-place classes with
-  // four-wave workgroups run two workgroups per CU
-  static constexpr int WPE = (!kPP && T == 256) ? 2 : 1;
+  // waves per SIMD the register allocation must leave room for.  Plans whose threads
+  // own R0 <= 4 points per surface are held to 256 VGPRs (two waves per SIMD): with
+  // the Gram-Schmidt loads issued in bursts the allocator would otherwise spill into
+  // AGPRs and halve the occupancy.
+  static constexpr int WPE = R0 <= 4 ? 2 : 1;
   // Gram-Schmidt sweeps take two basis vectors per turn when a thread owns few points
   static constexpr int GSV = (R0 <= 4) ? 2 : 1;
+  // surfaces per burst of Gram-Schmidt loads: GSV * SB * R0 loads in flight per lane
+  static constexpr int SB = (R0 <= 4) ? 2 : 1;
 
   struct OV {
     cplx v[2][R0];
@@ -92,6 +96,7 @@ struct Eng {
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int r = 0; r < R0; ++r) x.v[s][r] = g[s * N + pt(r)];
+    __builtin_amdgcn_sched_barrier(0);
   }
   static __device__ __forceinline__ void store(const OV& x, cplx* __restrict__ gp) {
     GQD_G cplx* g = opaque(gp);
@@ -132,7 +137,8 @@ struct Eng {
       const double nn = wave_sum(norm2(w));
       if (lane == 0) c.part[wv * c.kmax + K] = mk(nn, 0.0);
     }
-    // two basis vectors per turn so that their loads and reductions overlap
+    // two basis vectors per turn so that their loads and reductions overlap; all loads
+    // of a turn (or of one surface, for R0 = 8) are issued before the first use
 #pragma unroll 1
     for (int i = 0; i < K; i += GSV) {
       const bool two = GSV == 2 && i + 1 < K;
@@ -140,19 +146,28 @@ struct Eng {
       const GQD_G cplx* Vb = opaque(basis + (size_t)(two ? i + 1 : i) * VEC);
       double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
+      for (int s0 = 0; s0 < 2; s0 += SB) {
+        cplx a[SB][R0], b[SB][R0];
 #pragma unroll
-        for (int r = 0; r < R0; ++r) {
-          const cplx va = Va[s * N + pt(r)];
-          const cplx z = w.v[s][r];
-          ax += va.x * z.x + va.y * z.y;
-          ay += va.x * z.y - va.y * z.x;
-          if constexpr (GSV == 2) {
-            const cplx vb = Vb[s * N + pt(r)];
-            bx += vb.x * z.x + vb.y * z.y;
-            by += vb.x * z.y - vb.y * z.x;
+        for (int s = 0; s < SB; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) {
+            a[s][r] = Va[(s0 + s) * N + pt(r)];
+            if constexpr (GSV == 2) b[s][r] = Vb[(s0 + s) * N + pt(r)];
           }
-        }
+#pragma unroll
+        for (int s = 0; s < SB; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) {
+            const cplx z = w.v[s0 + s][r];
+            ax += a[s][r].x * z.x + a[s][r].y * z.y;
+            ay += a[s][r].x * z.y - a[s][r].y * z.x;
+            if constexpr (GSV == 2) {
+              bx += b[s][r].x * z.x + b[s][r].y * z.y;
+              by += b[s][r].x * z.y - b[s][r].y * z.x;
+            }
+          }
+      }
       ax = wave_sum(ax);
       ay = wave_sum(ay);
       if constexpr (GSV == 2) {
@@ -175,7 +190,8 @@ struct Eng {
     __syncthreads();
   }
 
-  // w -= sum_i h[i] V_i, i < K (h in LDS)
+  // w -= sum_i h[i] V_i, i < K (h in LDS).  All loads of a turn are issued before the
+  // first use, so that a wave keeps them in flight together.
   static __device__ void block_axpy(const cplx* __restrict__ basis, const GQD_L cplx* h, int K, OV& w) {
 #pragma unroll 1
     for (int i = 0; i < K; i += GSV) {
@@ -185,13 +201,23 @@ struct Eng {
       const cplx ha = h[i];
       const cplx hb = two ? h[i + 1] : mk(0.0, 0.0);
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
+      for (int s0 = 0; s0 < 2; s0 += SB) {
+        cplx a[SB][R0], b[SB][R0];
 #pragma unroll
-        for (int r = 0; r < R0; ++r) {
-          const cplx va = Va[s * N + pt(r)];
-          w.v[s][r] = csub(w.v[s][r], cmul(ha, va));
-          if constexpr (GSV == 2) w.v[s][r] = csub(w.v[s][r], cmul(hb, Vb[s * N + pt(r)]));
-        }
+        for (int s = 0; s < SB; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) {
+            a[s][r] = Va[(s0 + s) * N + pt(r)];
+            if constexpr (GSV == 2) b[s][r] = Vb[(s0 + s) * N + pt(r)];
+          }
+#pragma unroll
+        for (int s = 0; s < SB; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) {
+            w.v[s0 + s][r] = csub(w.v[s0 + s][r], cmul(ha, a[s][r]));
+            if constexpr (GSV == 2) w.v[s0 + s][r] = csub(w.v[s0 + s][r], cmul(hb, b[s][r]));
+          }
+      }
     }
   }
 
@@ -868,13 +894,25 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
             const GQD_G cplx* Vb = opaque(basis + (size_t)(two ? i + 1 : i) * E::VEC);
             const cplx ya = c.y[i];
             const cplx yb = two ? c.y[i + 1] : mk(0.0, 0.0);
+            constexpr int SB = E::SB;
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
+            for (int s0 = 0; s0 < 2; s0 += SB) {
+              cplx va[SB][R0], vb[SB][R0];
 #pragma unroll
-              for (int r = 0; r < R0; ++r) {
-                x.v[s][r] = cadd(x.v[s][r], cmul(ya, Va[s * N + E::pt(r)]));
-                if constexpr (E::GSV == 2) x.v[s][r] = cadd(x.v[s][r], cmul(yb, Vb[s * N + E::pt(r)]));
-              }
+              for (int s = 0; s < SB; ++s)
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                  va[s][r] = Va[(s0 + s) * N + E::pt(r)];
+                  if constexpr (E::GSV == 2) vb[s][r] = Vb[(s0 + s) * N + E::pt(r)];
+                }
+#pragma unroll
+              for (int s = 0; s < SB; ++s)
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                  x.v[s0 + s][r] = cadd(x.v[s0 + s][r], cmul(ya, va[s][r]));
+                  if constexpr (E::GSV == 2) x.v[s0 + s][r] = cadd(x.v[s0 + s][r], cmul(yb, vb[s][r]));
+                }
+            }
           }
           E::store(x, xg);
         }
@@ -903,13 +941,18 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         E::store(y, S3);
         double* gF = a.gF + im.foff;
         const double coef = -(2.0 * alpha / a.mass);
+        double tg[R0], g[R0];
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
           const int i0 = E::pt(r), i1 = N + E::pt(r);
-          const double t = cconjmul(S1[i0], S2[i1]).x - cconjmul(S1[i1], S2[i0]).x +
-                           cconjmul(S3[i0], S0[i1]).x - cconjmul(S3[i1], S0[i0]).x;
-          gF[E::pt(r)] += coef * t;
+          tg[r] = cconjmul(S1[i0], S2[i1]).x - cconjmul(S1[i1], S2[i0]).x +
+                  cconjmul(S3[i0], S0[i1]).x - cconjmul(S3[i1], S0[i0]).x;
         }
+#pragma unroll
+        for (int r = 0; r < R0; ++r) g[r] = gF[E::pt(r)];
+        __builtin_amdgcn_sched_barrier(0);  // all loads before the first store
+#pragma unroll
+        for (int r = 0; r < R0; ++r) gF[E::pt(r)] = g[r] + coef * tg[r];
         OV p, t;
         E::load(p, psi);
         E::load(t, S0);

@@ -261,13 +261,11 @@ template <int NL>
 __device__ __forceinline__ void block_map(bool row, int e, int& s, int& w, int& i) {
   s = e / (kLineWaves * NL);
   const int rem = e - s * kLineWaves * NL;
-  if (row) {
-    w = rem / NL;
-    i = rem - w * NL;
-  } else {
-    i = rem / kLineWaves;
-    w = rem - i * kLineWaves;
-  }
+  // rows: w = rem / NL, i = rem % NL; columns: i = rem / kLineWaves, w = rem % kLineWaves
+  // (selected as values, so that no private array of {w, i} is formed)
+  const int qr = rem / NL, qc = rem / kLineWaves;
+  w = row ? qr : rem - qc * kLineWaves;
+  i = row ? rem - qr * NL : qc;
 }
 
 // Line operation request of the propagation machine.
@@ -297,16 +295,44 @@ __device__ void line_op(const LineReq& q, const Ctx2& c, const K2Args& a, const 
   for (int b = g; b < 2 * E::NBA; b += a.G) {
     const bool row = b < E::NBA;
     const int l0 = (row ? b : b - E::NBA) * kLineWaves;
-    for (int e = threadIdx.x; e < 2 * kLineWaves * NL; e += kThreads2) {
-      int s, w, i;
-      block_map<NL>(row, e, s, w, i);
-      const int gi = line_gidx<NL>(row, s, l0 + w, i);
-      cplx v = q.src[gi];
-      if (q.src2) v = cadd(v, q.src2[gi]);
-      for (int k = 0; k < q.K; ++k) v = csub(v, cmul(c.coef[k], q.basis[(size_t)k * E::VEC + gi]));
-      if (q.scaled) v = cmul(q.scale, v);
-      if (row && q.copy_dst) q.copy_dst[gi] = v;
-      c.lines[(size_t)w * 4 * NL + s * NL + i] = v;
+    // EB elements per thread at a time, each source read for all of them before any is
+    // used, so that a wave keeps EB loads in flight (per element the operations and
+    // their order are those of the formula above)
+    constexpr int EPT = 2 * kLineWaves * NL / kThreads2;
+    constexpr int EB = EPT < 8 ? EPT : 8;
+    static_assert(EPT % EB == 0, "line block elements per thread");
+#pragma unroll 1
+    for (int e0 = 0; e0 < EPT; e0 += EB) {
+      int gi[EB], li[EB];
+      cplx v[EB], t[EB];
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        int s, w, i;
+        block_map<NL>(row, threadIdx.x + (e0 + u) * kThreads2, s, w, i);
+        gi[u] = line_gidx<NL>(row, s, l0 + w, i);
+        li[u] = w * 4 * NL + s * NL + i;
+        v[u] = q.src[gi[u]];
+      }
+      if (q.src2) {
+#pragma unroll
+        for (int u = 0; u < EB; ++u) t[u] = q.src2[gi[u]];
+#pragma unroll
+        for (int u = 0; u < EB; ++u) v[u] = cadd(v[u], t[u]);
+      }
+      for (int k = 0; k < q.K; ++k) {
+        const cplx* bk = q.basis + (size_t)k * E::VEC;
+        const cplx ck = c.coef[k];
+#pragma unroll
+        for (int u = 0; u < EB; ++u) t[u] = bk[gi[u]];
+#pragma unroll
+        for (int u = 0; u < EB; ++u) v[u] = csub(v[u], cmul(ck, t[u]));
+      }
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        if (q.scaled) v[u] = cmul(q.scale, v[u]);
+        if (row && q.copy_dst) q.copy_dst[gi[u]] = v[u];
+        c.lines[li[u]] = v[u];
+      }
     }
     __syncthreads();
     const int ln = l0 + wave;
@@ -320,14 +346,17 @@ __device__ void line_op(const LineReq& q, const Ctx2& c, const K2Args& a, const 
     const int d = row ? 1 : 0;  // rows move along q2 (F^(2)), columns along q1 (F^(1))
 #pragma unroll
     for (int r = 0; r < E::P; ++r) f[r] = F[d * E::NPTS + line_gidx<NL>(row, 0, ln, lane + 64 * r)];
-    const double ps = row ? im.ps1 : im.ps0;
+    // (selected as values: a select between two fields would become a private array)
+    const double ps0 = im.ps0, ps1 = im.ps1;
+    const double ps = row ? ps1 : ps0;
     line_kinetic<NL>(x, y, c, ps);
     line_couple<E::P>(y, x, f);
     if (q.opH) {
       cplx z[2][E::P];
       line_kinetic<NL>(y, z, c, ps);
       line_couple<E::P>(z, y, f);
-      const double inv2m = row ? a.inv2m1 : a.inv2m0;
+      const double m0 = a.inv2m0, m1 = a.inv2m1;
+      const double inv2m = row ? m1 : m0;
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -398,6 +427,10 @@ __device__ __forceinline__ double substep_tau2(int cc, const GammaTab& gt) {
 // the Rayleigh quotient of v_0 (classical Gram-Schmidt, a second pass when the first
 // removes all but kReorthRatio of |w|^2) and
 // Givens rotations on the Hessenberg matrix of 1 + i al H; stop at |g_(j+1)| <= tol |b|.
+// Chunk loops that sum over basis vectors take kChunkB elements per thread at a time,
+// reading each vector for all of them before using any (loads kept in flight together).
+constexpr int kChunkB = 4;
+
 template <int NL>
 __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   using E = G2<NL>;
@@ -709,10 +742,27 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         if (hn2 < kReorthRatio * w2) {
           // second pass: W = w - sum h_i v_i, then c_i = <v_i, W> and |W|^2 in one
           // reduction; the update by c is left to the next operand load
-          for (long long e = e0 + threadIdx.x; e < e1; e += T) {
-            cplx w = cadd(OR[e], OC[e]);
-            for (int i = 0; i <= j; ++i) w = csub(w, cmul(c.coef[i], basis[(size_t)i * E::VEC + e]));
-            W[e] = w;
+          for (long long eb = e0 + threadIdx.x; eb < e1; eb += kChunkB * T) {
+            cplx w[kChunkB], t[kChunkB];
+#pragma unroll
+            for (int u = 0; u < kChunkB; ++u) {
+              const long long e = eb + u * T;
+              w[u] = e < e1 ? OR[e] : mk(0.0, 0.0);
+              t[u] = e < e1 ? OC[e] : mk(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < kChunkB; ++u) w[u] = cadd(w[u], t[u]);
+            for (int i = 0; i <= j; ++i) {
+              const cplx* bi = basis + (size_t)i * E::VEC;
+              const cplx ci = c.coef[i];
+#pragma unroll
+              for (int u = 0; u < kChunkB; ++u) t[u] = eb + u * T < e1 ? bi[eb + u * T] : mk(0.0, 0.0);
+#pragma unroll
+              for (int u = 0; u < kChunkB; ++u) w[u] = csub(w[u], cmul(ci, t[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < kChunkB; ++u)
+              if (eb + u * T < e1) W[eb + u * T] = w[u];
           }
           chunk_dots(W, nullptr, j + 1, 2 * (j + 1));
           touched = true;
@@ -758,10 +808,21 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         }
         const int k = j + 1;
         gm_back_solve(k, c);
-        for (long long e = e0 + threadIdx.x; e < e1; e += T) {
-          cplx x = xg[e];
-          for (int i = 0; i < k; ++i) x = cadd(x, cmul(c.y[i], basis[(size_t)i * E::VEC + e]));
-          xg[e] = x;
+        for (long long eb = e0 + threadIdx.x; eb < e1; eb += kChunkB * T) {
+          cplx x[kChunkB], t[kChunkB];
+#pragma unroll
+          for (int u = 0; u < kChunkB; ++u) x[u] = eb + u * T < e1 ? xg[eb + u * T] : mk(0.0, 0.0);
+          for (int i = 0; i < k; ++i) {
+            const cplx* bi = basis + (size_t)i * E::VEC;
+            const cplx yi = c.y[i];
+#pragma unroll
+            for (int u = 0; u < kChunkB; ++u) t[u] = eb + u * T < e1 ? bi[eb + u * T] : mk(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < kChunkB; ++u) x[u] = cadd(x[u], cmul(yi, t[u]));
+          }
+#pragma unroll
+          for (int u = 0; u < kChunkB; ++u)
+            if (eb + u * T < e1) xg[eb + u * T] = x[u];
         }
         touched = true;
         if (cv) {
