@@ -39,14 +39,16 @@ N = 2048
 ORDER, SCHEME, METHOD = 8, "suzuki", "midp"
 TOL = 1e-14
 
-# HBM traffic of the propagation kernel from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# Memory traffic of the propagation kernel from two rocprofv3 --pmc passes (FETCH_SIZE, then
 # WRITE_SIZE) over one launch from t = 0 of this workload, scaled by what the counters read
-# for a 1 GiB device copy (FETCH_SIZE 0.5x, WRITE_SIZE 1.0x of the true bytes).  Valid only
-# for the device sources it was taken on: reported as null once they change.
+# for a 1 GiB device copy (FETCH_SIZE 0.5x, WRITE_SIZE 1.0x of the true bytes).  The
+# counters see what leaves the L2 caches, so reads served by the Infinity Cache count as
+# well.  Valid only for the device sources it was taken on: reported as null once they
+# change.
 TRAFFIC = {
-    "sources_sha256": "9522191fd77bb469685ca5afb56c85e1893fd81ed3a8d72e44bfded9e051e007",
-    "fetch_kib": 143522870.1875, "fetch_scale": 2.0,
-    "write_kib": 57001163.375, "write_scale": 1.0,
+    "sources_sha256": "75c17d31d8778b66dab1353109a8230cc662dc699915ea35017c68fffea39e29",
+    "fetch_kib": 109644230.0, "fetch_scale": 2.0,
+    "write_kib": 57014137.625, "write_scale": 1.0,
     "alg_bytes_same_launch": 331987550208.0,
     "summary": "profiles/k_run_2048_sz8_x1024.md",
 }
