@@ -41,3 +41,36 @@ def test_large_batch_is_repeatable_and_matches_oracle():
         r = float(np.linalg.norm(got[b] - ref) / np.linalg.norm(ref))
         print(f"packet {b}: rel {r:.2e}", flush=True)
         assert r <= 1e-12
+
+
+def test_2d_and_adjoint_launches_are_repeatable():
+    # the cooperative 2D kernel (grid barriers, partial sums in a fixed order) and the
+    # 1D reverse sweep (two solves and a gradient accumulation per substep) must also
+    # repeat bit for bit
+    from paper_1902_04661_amd import gqd
+    gqd.load_library()
+    it2 = I.two_dim_item(128, 128, p0=(2.0, -1.0))
+    prop2 = gqd.from_items([it2])
+    opts = gqd.SolverOpts(tol=1e-14, restart=32)
+    runs = []
+    for _ in range(2):
+        psi = prop2.pack([it2.psi0])
+        st = prop2.propagate(psi, "midp", "suzuki", 4, 10.0, 3, opts)
+        runs.append((psi, st.iterations))
+    print(f"2D: iterations {runs[0][1]} / {runs[1][1]}", flush=True)
+    assert torch.equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
+
+    items = I.adjoint_batch(64, seed=1, n=1024)
+    prop = gqd.from_items(items)
+    psiT = prop.pack([it.psi0 for it in items])
+    prop.propagate(psiT, "midp", "suzuki", 4, 4.0, 5, opts)
+    outs = []
+    for _ in range(2):
+        psi = psiT.clone()
+        lam = psiT.clone()
+        gF = torch.zeros(prop.f_size, dtype=torch.float64, device=psi.device)
+        prop.adjoint(psi, lam, gF, "suzuki", 4, 4.0, 5, opts)
+        outs.append((psi, lam, gF))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    print("adjoint: psi(0), lambda(0) and dL/dF repeat exactly", flush=True)
