@@ -65,7 +65,7 @@ def load_library(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() "
+        raise RuntimeError(f"{path} is not built: run python -m paper_1902_04661_amd.build "
                            "(there is no CPU fallback)")
     lib = ctypes.CDLL(path)
     vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong

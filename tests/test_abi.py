@@ -24,20 +24,20 @@ def test_header_declares_the_boundary():
         assert required in names
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="libgqd.so not built (run __graft_entry__.build())")
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgqd.so not built (run python -m paper_1902_04661_amd.build)")
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(LIB)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="libgqd.so not built (run __graft_entry__.build())")
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgqd.so not built (run python -m paper_1902_04661_amd.build)")
 def test_binding_lists_the_same_symbols():
     from paper_1902_04661_amd import gqd
     assert sorted(gqd.exported_symbols()) == declared_functions()
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="libgqd.so not built (run __graft_entry__.build())")
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgqd.so not built (run python -m paper_1902_04661_amd.build)")
 def test_invalid_arguments_fail_without_a_gpu():
     # argument validation happens before any device work
     from paper_1902_04661_amd import gqd
