@@ -155,12 +155,30 @@ K2Args base_args2(const gqd_handle* h) {
   return a;
 }
 
+void release_streams(gqd_handle* h) {
+  for (int c = 0; c < kNumClasses; ++c) {
+    if (h->side[c]) (void)hipStreamDestroy(h->side[c]);
+    if (h->ev_join[c]) (void)hipEventDestroy(h->ev_join[c]);
+    h->side[c] = nullptr;
+    h->ev_join[c] = nullptr;
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  h->ev_fork = nullptr;
+  h->streams_ready = false;
+}
+
+// Side streams and events, created on first use; a failure part way releases what was
+// created, so that a later call starts again from nothing.
 gqd_status ensure_streams(gqd_handle* h) {
   if (h->streams_ready) return GQD_OK;
-  GQD_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-  for (int c = 0; c < kNumClasses; ++c) {
-    GQD_HIP(hipStreamCreateWithFlags(&h->side[c], hipStreamNonBlocking));
-    GQD_HIP(hipEventCreateWithFlags(&h->ev_join[c], hipEventDisableTiming));
+  hipError_t e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+  for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
+    e = hipStreamCreateWithFlags(&h->side[c], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join[c], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    release_streams(h);
+    return hip_fail(e, "creating side streams");
   }
   h->streams_ready = true;
   return GQD_OK;
@@ -489,13 +507,7 @@ void gqd_destroy(gqd_handle* h) {
     if (h->d_lists[c]) (void)hipFree(h->d_lists[c]);
   if (h->d_tw) (void)hipFree(h->d_tw);
   if (h->d_stats) (void)hipFree(h->d_stats);
-  if (h->streams_ready) {
-    for (int c = 0; c < kNumClasses; ++c) {
-      (void)hipStreamDestroy(h->side[c]);
-      (void)hipEventDestroy(h->ev_join[c]);
-    }
-    (void)hipEventDestroy(h->ev_fork);
-  }
+  release_streams(h);
   delete h;
 }
 
