@@ -157,15 +157,22 @@ def adjoint_leg(gqd, inputs, dev, batch: int, nsteps: int) -> dict:
     opts = gqd.SolverOpts(tol=TOL, restart=32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    psi0 = torch.cat([ag.gaussian_packet(q, P["q0"][b], P["p0"][b], P["width"][b]).reshape(-1)
-                      for b in range(batch)])
-    F = torch.cat([ag.coupling(q, P["amp"][b], P["center"][b]) for b in range(batch)])
+    psi0 = ag.gaussian_packets(q, P["q0"], P["p0"], P["width"]).reshape(-1)
+    F = ag.couplings(q, P["amp"], P["center"]).reshape(-1)
     psiT = ag.propagate(prop, psi0, F, "suzuki", 4, 4.0, nsteps, opts)
     L = (items[0].dq * torch.abs(psiT.reshape(batch, 2, 1024)[:, 1]) ** 2).sum()
     L.backward()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # the plain forward solve of the same packets at the same tolerance, for comparison
+    psi = psi0.detach().clone()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prop.propagate(psi, "midp", "suzuki", 4, 4.0, nsteps, opts, stats=False)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t1
     return {"value": batch / el, "unit": "gradients/s", "params_per_gradient": 5, "seconds": el,
+            "forward_only_seconds": fwd, "gradient_over_forward": el / fwd,
             "workload": f"{batch} packets, N=1024, Suzuki order 4, dt=4, {nsteps} steps, forward + reverse"}
 
 
@@ -358,6 +365,12 @@ def main(argv=None):
         "adjoint": adjoint,
         "two_dim": twod,
         "adjoint_2d": adjoint2d,
+        # the batched and the differentiated forms against the plain one-packet solve, all
+        # at the same tolerance and step
+        "comparisons": {
+            "batch_over_single_packet": value / single["value"] if single else None,
+            "gradient_over_forward": adjoint.get("gradient_over_forward") if adjoint else None,
+        },
         "gmres": {"mean_iterations": iters / solves, "h_applies_per_step": applies / args.steps,
                   "solves_per_step": solves / args.steps,
                   "substeps_per_s": solves / (avg_kernel_s * args.steps),

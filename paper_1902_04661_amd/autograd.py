@@ -62,16 +62,31 @@ def grid(n: int, qmin: float, qmax: float, device) -> torch.Tensor:
 def gaussian_packet(q: torch.Tensor, q0, p0, width) -> torch.Tensor:
     """(2, n) complex128: a Gaussian on surface index 0 (|psi|^2 has standard deviation
     `width`), renormalised on the grid; differentiable in q0, p0, width."""
-    dq = float(q[1] - q[0])
+    dq = q[1] - q[0]
     x = q - q0
     g = torch.exp(torch.complex(-(x * x) / (4.0 * width * width), p0 * x))
     g = g / torch.sqrt(dq * torch.sum(torch.abs(g) ** 2))
     return torch.stack([g, torch.zeros_like(g)])
 
 
+def gaussian_packets(q: torch.Tensor, q0: torch.Tensor, p0: torch.Tensor, width: torch.Tensor) -> torch.Tensor:
+    """(B, 2, n): gaussian_packet for parameter vectors of length B, built in one go."""
+    dq = q[1] - q[0]
+    w = width[:, None]
+    x = q[None, :] - q0[:, None]
+    g = torch.exp(torch.complex(-(x * x) / (4.0 * w * w), p0[:, None] * x))
+    g = g / torch.sqrt(dq * torch.sum(torch.abs(g) ** 2, dim=1, keepdim=True))
+    return torch.stack([g, torch.zeros_like(g)], dim=1)
+
+
 def coupling(q: torch.Tensor, amp, center, cwidth: float = 0.5) -> torch.Tensor:
     """F12 = amp exp(-((q - center)/cwidth)^2), differentiable in amp and center."""
     return amp * torch.exp(-(((q - center) / cwidth) ** 2))
+
+
+def couplings(q: torch.Tensor, amp: torch.Tensor, center: torch.Tensor, cwidth: float = 0.5) -> torch.Tensor:
+    """(B, n): coupling for parameter vectors of length B."""
+    return amp[:, None] * torch.exp(-(((q[None, :] - center[:, None]) / cwidth) ** 2))
 
 
 def surface_population(psi: torch.Tensor, dq: float, surface: int = 1) -> torch.Tensor:

@@ -18,6 +18,21 @@ def test_torch_builders_match_numpy_inputs():
     assert abs(float(ag.surface_population(psi, it.dq, 0)) - 1.0) < 1e-14
 
 
+
+def test_batched_builders_match_the_per_packet_ones():
+    items = I.adjoint_batch(5, seed=1, n=512)
+    q = ag.grid(512, items[0].qmin, items[0].qmax, "cpu")
+    P = {k: torch.tensor([it.params[k] for it in items], dtype=torch.float64)
+         for k in ["q0", "p0", "width", "amp", "center"]}
+    psi = ag.gaussian_packets(q, P["q0"], P["p0"], P["width"])
+    F = ag.couplings(q, P["amp"], P["center"])
+    for b, it in enumerate(items):
+        one = ag.gaussian_packet(q, P["q0"][b], P["p0"][b], P["width"][b])
+        assert torch.equal(psi[b], one)
+        assert torch.equal(F[b], ag.coupling(q, P["amp"][b], P["center"][b]))
+        np.testing.assert_allclose(psi[b].numpy(), it.psi0, rtol=0, atol=1e-12)
+
+
 def test_ragged_batch_draws_are_seeded_and_in_range():
     a = I.ragged_batch_draws(64, seed=0)
     b = I.ragged_batch_draws(64, seed=0)
