@@ -5,5 +5,6 @@ from .gqd_oracle import (Model, SolverOpts, Stats, Counter, TRAP, MIDP, TRIPLE_J
                          dense_H, inner, norm, energy, populations, symplectic_form, gmres,
                          givens, explicit_euler, implicit_euler, trapezoidal_step,
                          midpoint_step, composition_gammas, substep_fractions, propagate,
-                         explicit_euler_propagate, implicit_euler_propagate, adjoint,
+                         explicit_euler_propagate, implicit_euler_propagate, sod_start,
+                         sod_propagate, adjoint,
                          population_loss)

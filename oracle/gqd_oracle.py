@@ -11,7 +11,8 @@ What it computes, in the paper's order and notation (hbar = 1, as in App. A):
   * the adiabatic molecular Hamiltonian H = (1/2) [p 1 - i F]^dag m^-1 [p 1 - i F] + V,
     Eq. (22), for S = 2 surfaces, applied in that factored form;
   * explicit Euler (Eq. 13) and implicit Euler (Eq. 14), the latter solved by GMRES
-    with the explicit-Euler initial guess (Sec. II.C);
+    with the explicit-Euler initial guess (Sec. II.C), and second-order differencing
+    (Eq. 16) started by a second-order Runge-Kutta step (Sec. III);
   * trapezoidal rule (Eq. 18) and implicit midpoint (Eq. 19);
   * triple-jump (Eq. 20) and Suzuki-fractal (Eq. 21) recursive symmetric compositions
     (Sec. II.D);
@@ -435,6 +436,29 @@ def implicit_euler_propagate(model: Model, psi0: np.ndarray, dt: float, nsteps: 
     for _ in range(nsteps):
         psi = implicit_euler(model, psi, dt, opts)
     return psi
+
+
+def sod_start(model: Model, psi0: np.ndarray, dt: float) -> np.ndarray:
+    """psi(-dt) from psi(0) by one second-order Runge-Kutta step of length -dt (Sec. III,
+    discussion of Fig. 7).  For the linear equation d psi/dt = -i H psi every two-stage
+    second-order scheme gives the same step, the second-order Taylor polynomial:
+    psi(-dt) = (1 + i dt H - dt^2 H^2 / 2) psi(0)."""
+    h1 = apply_H(model, psi0)
+    h2 = apply_H(model, h1)
+    return psi0 + 1j * dt * h1 - 0.5 * dt * dt * h2
+
+
+def sod_propagate(model: Model, psi0: np.ndarray, dt: float, nsteps: int,
+                  return_previous: bool = False):
+    """Second-order differencing, Eq. (16): psi(t + dt) = psi(t - dt) - 2 i dt H psi(t),
+    started from psi(0) and psi(-dt) = sod_start(psi(0)).  With return_previous, also
+    psi(t_f - dt), the second state the two-step recurrence carries."""
+    prev = sod_start(model, psi0, dt)
+    cur = np.array(psi0, dtype=np.complex128, copy=True)
+    for _ in range(nsteps):
+        nxt = prev - 2j * dt * apply_H(model, cur)
+        prev, cur = cur, nxt
+    return (cur, prev) if return_previous else cur
 
 
 # ---------------------------------------------------------------------------- adjoint
