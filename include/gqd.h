@@ -73,10 +73,16 @@ typedef enum {
   GQD_ERR_STATE = -7          /* surfaces or workspace not set */
 } gqd_status;
 
-/* Base second-order method (Sec. II.C). */
+/* Base method.  The geometric second-order methods (Sec. II.C) are composed to higher
+ * orders; the elementary methods of Sec. II.B are the paper's non-geometric controls
+ * and are not composed. */
 typedef enum {
-  GQD_TRAP = 0, /* trapezoidal rule, U_impl(h/2) U_expl(h/2), Eq. (18) */
-  GQD_MIDP = 1  /* implicit midpoint, U_expl(h/2) U_impl(h/2), Eq. (19) */
+  GQD_TRAP = 0,           /* trapezoidal rule, U_impl(h/2) U_expl(h/2), Eq. (18) */
+  GQD_MIDP = 1,           /* implicit midpoint, U_expl(h/2) U_impl(h/2), Eq. (19) */
+  GQD_EULER_EXPLICIT = 2, /* psi' = (1 - i dt H) psi, Eq. (13) */
+  GQD_EULER_IMPLICIT = 3, /* psi' = (1 + i dt H)^-1 psi, Eq. (14), GMRES as for TRAP/MIDP */
+  GQD_SOD = 4             /* second-order differencing psi(t + dt) = psi(t - dt)
+                             - 2 i dt H psi(t), Eq. (16) */
 } gqd_method;
 
 /* Recursive symmetric composition (Sec. II.D). */
@@ -143,14 +149,22 @@ gqd_status gqd_set_surfaces(gqd_handle* h, const double* V, const double* F);
 gqd_status gqd_apply_H(gqd_handle* h, const void* psi_in, void* psi_out, void* stream);
 
 /* One base step of length dt in place: trapezoidal rule or implicit midpoint, each
- * with its implicit half solved by GMRES from the explicit-Euler guess (Sec. II.C). */
+ * with its implicit half solved by GMRES from the explicit-Euler guess (Sec. II.C).
+ * (The elementary methods step through gqd_propagate.) */
 gqd_status gqd_implicit_step(gqd_handle* h, gqd_method m, double dt, void* psi,
                              const gqd_solver_opts* o, gqd_stats* st, void* stream);
 
 /* nsteps steps of length dt in place, each the recursive symmetric composition of the
  * base method to the given even order (2, 4, 6, 8, 10): 3^(order/2-1) triple-jump or
  * 5^(order/2-1) Suzuki substeps, gamma_1 applied first (Sec. II.D).  dt may be
- * negative (backward propagation). */
+ * negative (backward propagation).
+ * The elementary methods take order 1 (both Euler methods) or 2 (GQD_SOD), ignore the
+ * scheme and run on 1D grids only (GQD_ERR_UNSUPPORTED in 2D).  GQD_SOD carries two
+ * states; every call starts it afresh from psi(0) = psi and
+ * psi(-dt) = (1 + i dt H - dt^2 H^2 / 2) psi(0), one second-order Runge-Kutta step
+ * backwards (Sec. III), so one run is one call with its total step count.  It is
+ * stable only for |dt| < 1 / E_max, E_max the largest |eigenvalue| of H (Eq. A48);
+ * beyond it the state grows without bound (GQD_ERR_NONFINITE once it overflows). */
 gqd_status gqd_propagate(gqd_handle* h, gqd_method m, gqd_scheme s, int order, double dt,
                          long long nsteps, void* psi, const gqd_solver_opts* o,
                          gqd_stats* st, void* stream);

@@ -568,17 +568,32 @@ gqd_status gqd_apply_H(gqd_handle* h, const void* in, void* out, void* stream) {
   return for_each_class(h, (hipStream_t)stream, a, launch_apply_h);
 }
 
+static bool elementary(gqd_method m) { return m == GQD_EULER_EXPLICIT || m == GQD_EULER_IMPLICIT || m == GQD_SOD; }
+
+static int method_code(gqd_method m) {
+  switch (m) {
+    case GQD_TRAP: return kTrap;
+    case GQD_EULER_EXPLICIT: return kEulerExpl;
+    case GQD_EULER_IMPLICIT: return kEulerImpl;
+    case GQD_SOD: return kSod;
+    default: return kMidp;
+  }
+}
+
 static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, double dt,
                                  long long nsteps, const double* dt_item, const long long* nsteps_item,
                                  void* psi, const gqd_solver_opts* o, gqd_stats* st, void* stream) {
   gqd_status s = ready(h, true, o);
   if (s != GQD_OK) return s;
   if (!psi) return fail(GQD_ERR_INVALID, "NULL state pointer");
-  if (m != GQD_TRAP && m != GQD_MIDP) return fail(GQD_ERR_INVALID, "unknown method");
+  if (m != GQD_TRAP && m != GQD_MIDP && !elementary(m)) return fail(GQD_ERR_INVALID, "unknown method");
+  if (elementary(m) && order != (m == GQD_SOD ? 2 : 1))
+    return fail(GQD_ERR_INVALID, "the Euler methods take order 1 and second-order differencing order 2");
   if (!std::isfinite(dt)) return fail(GQD_ERR_INVALID, "dt must be finite");
   if (nsteps < 0) return fail(GQD_ERR_INVALID, "nsteps must be >= 0");
   hipStream_t strm = (hipStream_t)stream;
   if (h->dims == 2) {
+    if (elementary(m)) return fail(GQD_ERR_UNSUPPORTED, "the elementary methods run on 1D grids");
     if (dt_item || nsteps_item) return fail(GQD_ERR_UNSUPPORTED, "per-item steps are available on 1D grids");
     K2Args a = base_args2(h);
     s = make_gammas(sch, order, &a.gt);
@@ -595,13 +610,14 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
     return st ? collect_stats(h, strm, st) : GQD_OK;
   }
   KArgs a = base_args(h);
-  s = make_gammas(sch, order, &a.gt);
+  // the elementary methods take whole steps: a one-substep table (tau = 1)
+  s = elementary(m) ? make_gammas(GQD_SUZUKI, 2, &a.gt) : make_gammas(sch, order, &a.gt);
   if (s != GQD_OK) return s;
   a.psi = (double2*)psi;
   a.work = (double2*)h->work;
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
   a.mode = 0;
-  a.method = (m == GQD_TRAP) ? kTrap : kMidp;
+  a.method = method_code(m);
   a.dt = dt;
   a.nsteps = nsteps;
   a.dt_item = dt_item;
@@ -667,7 +683,8 @@ gqd_status gqd_autotune(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, 
   gqd_status s = ready(h, true, o);
   if (s != GQD_OK) return s;
   if (!psi) return fail(GQD_ERR_INVALID, "NULL state pointer");
-  if (m != GQD_TRAP && m != GQD_MIDP) return fail(GQD_ERR_INVALID, "unknown method");
+  if (m != GQD_TRAP && m != GQD_MIDP)
+    return fail(GQD_ERR_INVALID, "the autotuner takes the trapezoidal rule or the implicit midpoint");
   if (!std::isfinite(dt)) return fail(GQD_ERR_INVALID, "dt must be finite");
   if (nsteps < 1) return fail(GQD_ERR_INVALID, "nsteps must be >= 1");
   if (radices)
@@ -729,6 +746,8 @@ gqd_status gqd_autotune(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, 
 
 gqd_status gqd_implicit_step(gqd_handle* h, gqd_method m, double dt, void* psi, const gqd_solver_opts* o,
                              gqd_stats* st, void* stream) {
+  if (m != GQD_TRAP && m != GQD_MIDP)
+    return fail(GQD_ERR_INVALID, "gqd_implicit_step takes the trapezoidal rule or the implicit midpoint");
   return gqd_propagate(h, m, GQD_SUZUKI, 2, dt, 1, psi, o, st, stream);
 }
 

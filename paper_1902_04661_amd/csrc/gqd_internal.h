@@ -59,7 +59,8 @@ struct GammaTab {
   double mid[kMaxLevels];
 };
 
-enum Method { kTrap = 0, kMidp = 1 };
+// geometric base methods (composed), then the elementary controls (not composed)
+enum Method { kTrap = 0, kMidp = 1, kEulerExpl = 2, kEulerImpl = 3, kSod = 4 };
 
 struct KArgs {
   const ItemMeta* items;

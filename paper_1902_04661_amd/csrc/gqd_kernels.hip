@@ -532,7 +532,12 @@ enum Pc {
   kAdjAfterPhi,   // adjoint: phi solved
   kAdjAfterMu,    // adjoint: mu solved
   kAdjAphi,       // adjoint: have A phi
-  kAdjAmu         // adjoint: have A mu
+  kAdjAmu,        // adjoint: have A mu
+  kExplAfter,     // explicit Euler: have H psi
+  kImplAfter,     // implicit Euler: x solved
+  kSodStart,      // second-order differencing: have H psi(0)
+  kSodStart2,     // second-order differencing: have H H psi(0)
+  kSodStep        // second-order differencing: have H psi(t)
 };
 
 // Whole-call propagation (mode 0) or reverse sweep (mode 1) of one item per workgroup.
@@ -590,7 +595,8 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
 
   long long n = 0;
   int cc = adj ? a.gt.count - 1 : 0;
-  double alpha = 0.0;
+  double alpha = 0.0;  // half the substep (geometric methods), the whole step (elementary)
+  bool sod_started = false;
 
   // operator request: H - opshift applied to opsrc (opshift = 0 outside Arnoldi)
   bool pending = false, opH = false;
@@ -693,6 +699,16 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
     switch (pc) {
       case kSubstep: {
         if (n >= nsteps) goto done;
+        if (a.method >= kEulerExpl) {  // elementary methods: whole steps, tau = 1
+          alpha = substep_tau(cc, a.gt) * dt;
+          if (a.method == kEulerImpl) {
+            solve_begin(psi, S0, alpha, kImplAfter);
+          } else {
+            request(psi, true);
+            pc = a.method == kEulerExpl ? kExplAfter : (sod_started ? kSodStep : kSodStart);
+          }
+          break;
+        }
         alpha = 0.5 * (substep_tau(cc, a.gt) * dt);
         if (adj) {
           solve_begin(psi, S0, -alpha, kAdjAfterPhi);
@@ -968,6 +984,64 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
           for (int r = 0; r < R0; ++r) p.v[s][r] = csub(cscale(t.v[s][r], 2.0), p.v[s][r]);
         E::store(p, lam);
+        advance();
+        break;
+      }
+      case kExplAfter: {  // psi' = psi - i dt H psi (Eq. 13)
+        OV p;
+        E::load(p, psi);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) p.v[s][r] = csub(p.v[s][r], cmul_is(y.v[s][r], alpha));
+        E::store(p, psi);
+        advance();
+        break;
+      }
+      case kImplAfter: {  // psi' = (1 + i dt H)^-1 psi (Eq. 14), solved into S0
+        OV p;
+        E::load(p, S0);
+        E::store(p, psi);
+        advance();
+        break;
+      }
+      case kSodStart: {  // H psi(0) kept for the start and the first step; ask for H H psi(0)
+        E::store(y, S2);
+        request(S2, true);
+        pc = kSodStart2;
+        break;
+      }
+      case kSodStart2: {
+        // psi(-dt) = psi(0) + i dt H psi(0) - dt^2/2 H H psi(0), one second-order
+        // Runge-Kutta step backwards (Sec. III); then the first step of Eq. (16),
+        // psi(dt) = psi(-dt) - 2 i dt H psi(0); S1 keeps the previous state psi(0)
+        OV p, h1, q;
+        E::load(p, psi);
+        E::load(h1, S2);
+        const double half2 = -0.5 * alpha * alpha;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) {
+            const cplx prev = cadd(cadd(p.v[s][r], cmul_is(h1.v[s][r], alpha)), cscale(y.v[s][r], half2));
+            q.v[s][r] = csub(prev, cmul_is(h1.v[s][r], 2.0 * alpha));
+          }
+        E::store(p, S1);
+        E::store(q, psi);
+        sod_started = true;
+        advance();
+        break;
+      }
+      case kSodStep: {  // psi(t + dt) = psi(t - dt) - 2 i dt H psi(t) (Eq. 16)
+        OV p, q;
+        E::load(p, psi);
+        E::load(q, S1);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) q.v[s][r] = csub(q.v[s][r], cmul_is(y.v[s][r], 2.0 * alpha));
+        E::store(p, S1);
+        E::store(q, psi);
         advance();
         break;
       }

@@ -18,8 +18,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgqd.so")
 
 TRAP, MIDP = 0, 1
+# the paper's elementary, non-geometric methods (Eqs. 13, 14, 16): order 1, 1 and 2,
+# not composed, 1D only
+EULER_EXPLICIT, EULER_IMPLICIT, SOD = 2, 3, 4
 TRIPLE_JUMP, SUZUKI = 0, 1
-_METHODS = {"trap": TRAP, "midp": MIDP, TRAP: TRAP, MIDP: MIDP}
+_METHODS = {"trap": TRAP, "midp": MIDP, "euler_explicit": EULER_EXPLICIT,
+            "euler_implicit": EULER_IMPLICIT, "sod": SOD}
+_METHODS.update({v: v for v in list(_METHODS.values())})
 _SCHEMES = {"triple_jump": TRIPLE_JUMP, "suzuki": SUZUKI, TRIPLE_JUMP: TRIPLE_JUMP, SUZUKI: SUZUKI}
 SIZES = (256, 512, 1024, 2048, 4096)
 
