@@ -46,9 +46,9 @@ TOL = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "75c17d31d8778b66dab1353109a8230cc662dc699915ea35017c68fffea39e29",
-    "fetch_kib": 109644230.0, "fetch_scale": 2.0,
-    "write_kib": 57014137.625, "write_scale": 1.0,
+    "sources_sha256": "c3e56076b59b965a8d61ce6f104747cccaf3ac7467a31e2e98d87534b64364a0",
+    "fetch_kib": 109210476.125, "fetch_scale": 2.0,
+    "write_kib": 57014379.375, "write_scale": 1.0,
     "alg_bytes_same_launch": 331987550208.0,
     "summary": "profiles/k_run_2048_sz8_x1024.md",
 }
@@ -99,6 +99,34 @@ def ragged_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
     return {"value": pts * steps / el, "unit": "grid-point·steps/s", "ms_per_step": 1e3 * el / steps,
             "alg_GBps": byts / el / 1e9, "hbm_frac": byts / el / 1e9 / HBM_PEAK_GBS,
             "workload": f"{batch} packets, N in {{256..4096}} (sum {pts}), Suzuki order 6, dt={DT_STAR}"}
+
+
+SOD_DT = 0.15  # below 1 / E_max of the N = 2048 grid on [3, 16) (E_max ~ 4.3 Ha)
+
+
+def elementary_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
+    """Second-order differencing (Eq. 16) on the benchmark's packet replicated `batch`
+    times, at the largest round step below its stability limit.  One H application per
+    step and grid point; algorithmic traffic 128 bytes per grid point per step (read
+    psi(t) and psi(t - dt), write psi(t + dt) and the new previous state)."""
+    import torch
+    it = inputs.nai_like_item(N)
+    prop = gqd.from_items([it] * batch, device=dev)
+    psi = prop.pack([it.psi0] * batch)
+    prop.propagate(psi, "sod", "suzuki", 2, SOD_DT, 2, stats=False)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    prop.propagate(psi, "sod", "suzuki", 2, SOD_DT, steps, stats=False)
+    e1.record(s)
+    torch.cuda.synchronize()
+    el = e0.elapsed_time(e1) * 1e-3
+    gps = batch * N * steps / el
+    return {"value": gps, "unit": "grid-point·steps/s", "ms_per_step": 1e3 * el / steps,
+            "us_per_h_apply_per_packet": 1e6 * el * 256 / (batch * (steps + 1)),
+            "alg_GBps": 128.0 * gps / 1e9, "hbm_frac": 128.0 * gps / 1e9 / HBM_PEAK_GBS,
+            "workload": f"second-order differencing, {batch} x N={N} packet, dt={SOD_DT}, {steps} steps"}
 
 
 def twod_leg(gqd, inputs, dev, steps: int) -> dict:
@@ -217,6 +245,7 @@ def main(argv=None):
     ap.add_argument("--adjoint-batch", type=int, default=256)
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--twod-steps", type=int, default=100)
+    ap.add_argument("--sod-steps", type=int, default=400, help="elementary-method leg (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default transform plans")
     ap.add_argument("--adjoint2d-steps", type=int, default=400)
     ap.add_argument("--no-cpu", action="store_true")
@@ -317,6 +346,11 @@ def main(argv=None):
         adjoint = adjoint_leg(gqd, inputs, dev, args.adjoint_batch, args.adjoint_steps)
         print(f"[bench] adjoint: {adjoint['value']:.1f} gradients/s", file=sys.stderr, flush=True)
 
+    elementary = {}
+    if args.sod_steps > 0:
+        elementary = elementary_leg(gqd, inputs, dev, args.batch, args.sod_steps)
+        print(f"[bench] second-order differencing: {elementary['value']:.3e} gp.steps/s "
+              f"({100 * elementary['hbm_frac']:.0f} % of HBM peak)", file=sys.stderr, flush=True)
     twod = {}
     if args.twod_steps > 0:
         twod = twod_leg(gqd, inputs, dev, args.twod_steps)
@@ -365,6 +399,7 @@ def main(argv=None):
         "adjoint": adjoint,
         "two_dim": twod,
         "adjoint_2d": adjoint2d,
+        "elementary": elementary,
         # the batched and the differentiated forms against the plain one-packet solve, all
         # at the same tolerance and step
         "comparisons": {
