@@ -6,5 +6,6 @@ from .gqd_oracle import (Model, SolverOpts, Stats, Counter, TRAP, MIDP, TRIPLE_J
                          givens, explicit_euler, implicit_euler, trapezoidal_step,
                          midpoint_step, composition_gammas, substep_fractions, propagate,
                          explicit_euler_propagate, implicit_euler_propagate, sod_start,
-                         sod_propagate, adjoint,
+                         sod_propagate, diabatic_to_adiabatic, to_adiabatic, apply_H_diabatic,
+                         exp_W, exp_T, split_operator_step, split_operator_propagate, adjoint,
                          population_loss)

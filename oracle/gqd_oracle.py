@@ -13,6 +13,9 @@ What it computes, in the paper's order and notation (hbar = 1, as in App. A):
   * explicit Euler (Eq. 13) and implicit Euler (Eq. 14), the latter solved by GMRES
     with the explicit-Euler initial guess (Sec. II.C), and second-order differencing
     (Eq. 16) started by a second-order Runge-Kutta step (Sec. III);
+  * the two-state diabatic -> adiabatic transformation (Sec. II.F, Eqs. 24-28) and, in
+    the diabatic representation, the composed second-order split-operator method of
+    Table I, as an independent check of the adiabatic propagation;
   * trapezoidal rule (Eq. 18) and implicit midpoint (Eq. 19);
   * triple-jump (Eq. 20) and Suzuki-fractal (Eq. 21) recursive symmetric compositions
     (Sec. II.D);
@@ -459,6 +462,84 @@ def sod_propagate(model: Model, psi0: np.ndarray, dt: float, nsteps: int,
         nxt = prev - 2j * dt * apply_H(model, cur)
         prev, cur = cur, nxt
     return (cur, prev) if return_previous else cur
+
+
+# --------------------------------------------------------------- diabatic representation
+
+
+def diabatic_to_adiabatic(W: np.ndarray, dW: np.ndarray):
+    """Two-state diabatic -> adiabatic (Sec. II.F, Eqs. 24-28) for W = (W11, W22, W12)
+    and its derivatives dW on a grid.  Returns (V, F12, cos, sin):
+      V = (V_1, V_2) = Wbar +- sqrt((Delta W / 2)^2 + W12^2), Delta W = W22 - W11;
+      O(q) of Eq. (26) is the rotation by theta with cos = W12 / n, sin = Delta / n,
+      Delta = V_1 - W11, i.e. tan(theta) = Delta / W12, equivalently
+      tan(2 theta) = 2 W12 / (W11 - W22) (theta in (0, pi/2) where W12 > 0);
+      F = O^T O' (Eq. 27) gives F12 = -theta' = (Delta W W12' - W12 Delta W') /
+      (Delta W^2 + 4 W12^2), which is Eq. (28) rewritten without the cancellation in
+      Delta = V_1 - W11 far from the crossing.
+    The adiabatic state is psi = O^T psi_diab (Eq. 25): psi_1 = cos d1 + sin d2,
+    psi_2 = -sin d1 + cos d2."""
+    W11, W22, W12 = W
+    dW11, dW22, dW12 = dW
+    wbar = 0.5 * (W11 + W22)
+    dw = W22 - W11
+    r = np.sqrt((0.5 * dw) ** 2 + W12 ** 2)
+    V = np.stack([wbar + r, wbar - r])
+    theta = 0.5 * np.arctan2(2.0 * W12, W11 - W22)
+    ddw = dW22 - dW11
+    F12 = (dw * dW12 - W12 * ddw) / (dw * dw + 4.0 * W12 * W12)
+    return V, F12, np.cos(theta), np.sin(theta)
+
+
+def to_adiabatic(psi_diab: np.ndarray, c: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """psi = O(q)^T psi_diab pointwise (Eq. 25)."""
+    d1, d2 = psi_diab
+    return np.stack([c * d1 + s * d2, -s * d1 + c * d2])
+
+
+def apply_H_diabatic(n: int, qmin: float, qmax: float, mass: float, W: np.ndarray,
+                     psi: np.ndarray) -> np.ndarray:
+    """H_diab psi = p^2/(2m) psi + W psi (the diabatic Hamiltonian of Sec. II.F)."""
+    p = momentum_grid(n, qmax - qmin)
+    kin = np.fft.ifft((p * p / (2.0 * mass)) * np.fft.fft(psi, axis=-1), axis=-1)
+    W11, W22, W12 = W
+    return kin + np.stack([W11 * psi[0] + W12 * psi[1], W12 * psi[0] + W22 * psi[1]])
+
+
+def exp_W(W: np.ndarray, psi: np.ndarray, tau: float) -> np.ndarray:
+    """exp(-i W(q) tau) applied pointwise, from the eigendecomposition of each 2 x 2
+    W(q) (a library eigensolver as a step)."""
+    W11, W22, W12 = W
+    M = np.stack([np.stack([W11, W12], -1), np.stack([W12, W22], -1)], -2)  # (n, 2, 2)
+    lam, U = np.linalg.eigh(M)
+    E = U @ (np.exp(-1j * tau * lam)[..., None] * np.swapaxes(U, -1, -2))
+    return np.einsum("nij,jn->in", E, psi)
+
+
+def exp_T(n: int, qmin: float, qmax: float, mass: float, psi: np.ndarray, tau: float) -> np.ndarray:
+    """exp(-i p^2 tau / 2m) on both components, diagonal in the Fourier basis."""
+    p = momentum_grid(n, qmax - qmin)
+    return np.fft.ifft(np.exp(-1j * tau * p * p / (2.0 * mass)) * np.fft.fft(psi, axis=-1), axis=-1)
+
+
+def split_operator_step(n, qmin, qmax, mass, W, psi, h: float) -> np.ndarray:
+    """The standard second-order (Strang) splitting the paper lists among its reference
+    methods (Table I): exp(-i W h/2) exp(-i T h) exp(-i W h/2)."""
+    psi = exp_W(W, psi, 0.5 * h)
+    psi = exp_T(n, qmin, qmax, mass, psi, h)
+    return exp_W(W, psi, 0.5 * h)
+
+
+def split_operator_propagate(n, qmin, qmax, mass, W, psi0: np.ndarray, scheme: str, order: int,
+                             dt: float, nsteps: int) -> np.ndarray:
+    """nsteps steps of the split-operator step composed like the implicit methods
+    (Sec. II.D): substep c has length tau_c dt, in list order."""
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    taus = substep_fractions(scheme, order)
+    for _ in range(nsteps):
+        for t in taus:
+            psi = split_operator_step(n, qmin, qmax, mass, W, psi, t * dt)
+    return psi
 
 
 # ---------------------------------------------------------------------------- adjoint

@@ -150,6 +150,47 @@ def adjoint_batch(batch: int = 256, seed: int = 1, n: int = 1024) -> List[Item1D
             for b in range(batch)]
 
 
+# ------------------------------------------------------------------ diabatic model
+
+@dataclass
+class DiabaticItem:
+    """A two-state diabatic model on a 1D grid: H_diab = p^2 / 2m + W(q) with the real
+    symmetric W of Sec. II.F, its first derivatives, and a packet on diabatic state 1."""
+    n: int
+    qmin: float
+    qmax: float
+    mass: float
+    W: np.ndarray    # (3, n): W11, W22, W12
+    dW: np.ndarray   # (3, n): their derivatives in q
+    psi0: np.ndarray  # (2, n) diabatic components
+
+    @property
+    def q(self) -> np.ndarray:
+        return uniform_grid(self.n, self.qmin, self.qmax)
+
+    @property
+    def dq(self) -> float:
+        return (self.qmax - self.qmin) / self.n
+
+
+def diabatic_crossing_item(n: int = 2048, qmin: float = QMIN, qmax: float = QMAX,
+                           k: float = 0.035, centers=(5.0, 7.0), c12: float = 0.003,
+                           x12: float = 6.0, w12: float = 1.0, q0: float = 5.0, p0: float = 40.0,
+                           width: float = 0.12, mass: float = MASS) -> DiabaticItem:
+    """Two shifted harmonic diabats W_ii = k (q - c_i)^2 / 2 crossing once (at 6 bohr),
+    coupled by W12 = c12 exp(-((q - x12) / w12)^2); a Gaussian on diabat 1 whose
+    momentum carries it through the crossing.  k = 0.035 gives the packet's width 0.12
+    as the harmonic ground state of diabat 1 at m = 3.5e4."""
+    q = uniform_grid(n, qmin, qmax)
+    W11 = 0.5 * k * (q - centers[0]) ** 2
+    W22 = 0.5 * k * (q - centers[1]) ** 2
+    g = np.exp(-(((q - x12) / w12) ** 2))
+    W12 = c12 * g
+    dW = np.stack([k * (q - centers[0]), k * (q - centers[1]), -2.0 * (q - x12) / (w12 * w12) * W12])
+    return DiabaticItem(n, qmin, qmax, mass, np.stack([W11, W22, W12]), dW,
+                        gaussian_packet_1d(q, q0, p0, width))
+
+
 # --------------------------------------------------------------------------- 2D model
 
 @dataclass
