@@ -81,8 +81,13 @@ typedef enum {
   GQD_MIDP = 1,           /* implicit midpoint, U_expl(h/2) U_impl(h/2), Eq. (19) */
   GQD_EULER_EXPLICIT = 2, /* psi' = (1 - i dt H) psi, Eq. (13) */
   GQD_EULER_IMPLICIT = 3, /* psi' = (1 + i dt H)^-1 psi, Eq. (14), GMRES as for TRAP/MIDP */
-  GQD_SOD = 4             /* second-order differencing psi(t + dt) = psi(t - dt)
+  GQD_SOD = 4,            /* second-order differencing psi(t + dt) = psi(t - dt)
                              - 2 i dt H psi(t), Eq. (16) */
+  GQD_SPLIT_OPERATOR = 5  /* DIABATIC representation: H = p^2/2m + W(q) with the real
+                             symmetric W read from the surfaces as V = (W11, W22),
+                             F = W12; the second-order splitting exp(-i W h/2)
+                             exp(-i T h) exp(-i W h/2) of Table I, composed like
+                             TRAP and MIDP (Sec. II.D).  1D only. */
 } gqd_method;
 
 /* Recursive symmetric composition (Sec. II.D). */

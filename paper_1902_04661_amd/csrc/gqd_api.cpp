@@ -576,6 +576,7 @@ static int method_code(gqd_method m) {
     case GQD_EULER_EXPLICIT: return kEulerExpl;
     case GQD_EULER_IMPLICIT: return kEulerImpl;
     case GQD_SOD: return kSod;
+    case GQD_SPLIT_OPERATOR: return kSplit;
     default: return kMidp;
   }
 }
@@ -586,14 +587,16 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   gqd_status s = ready(h, true, o);
   if (s != GQD_OK) return s;
   if (!psi) return fail(GQD_ERR_INVALID, "NULL state pointer");
-  if (m != GQD_TRAP && m != GQD_MIDP && !elementary(m)) return fail(GQD_ERR_INVALID, "unknown method");
+  if (m != GQD_TRAP && m != GQD_MIDP && m != GQD_SPLIT_OPERATOR && !elementary(m))
+    return fail(GQD_ERR_INVALID, "unknown method");
   if (elementary(m) && order != (m == GQD_SOD ? 2 : 1))
     return fail(GQD_ERR_INVALID, "the Euler methods take order 1 and second-order differencing order 2");
   if (!std::isfinite(dt)) return fail(GQD_ERR_INVALID, "dt must be finite");
   if (nsteps < 0) return fail(GQD_ERR_INVALID, "nsteps must be >= 0");
   hipStream_t strm = (hipStream_t)stream;
   if (h->dims == 2) {
-    if (elementary(m)) return fail(GQD_ERR_UNSUPPORTED, "the elementary methods run on 1D grids");
+    if (elementary(m) || m == GQD_SPLIT_OPERATOR)
+      return fail(GQD_ERR_UNSUPPORTED, "the elementary and split-operator methods run on 1D grids");
     if (dt_item || nsteps_item) return fail(GQD_ERR_UNSUPPORTED, "per-item steps are available on 1D grids");
     K2Args a = base_args2(h);
     s = make_gammas(sch, order, &a.gt);
@@ -623,7 +626,7 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   a.dt_item = dt_item;
   a.nsteps_item = nsteps_item;
   a.hpsi_valid = 0;
-  s = for_each_class(h, strm, a, launch_run);
+  s = for_each_class(h, strm, a, m == GQD_SPLIT_OPERATOR ? launch_split : launch_run);
   if (s != GQD_OK) return s;
   return st ? collect_stats(h, strm, st) : GQD_OK;
 }

@@ -60,7 +60,8 @@ struct GammaTab {
 };
 
 // geometric base methods (composed), then the elementary controls (not composed)
-enum Method { kTrap = 0, kMidp = 1, kEulerExpl = 2, kEulerImpl = 3, kSod = 4 };
+// (kSplit: the split-operator method of the diabatic representation, composed)
+enum Method { kTrap = 0, kMidp = 1, kEulerExpl = 2, kEulerImpl = 3, kSod = 4, kSplit = 5 };
 
 struct KArgs {
   const ItemMeta* items;
@@ -232,6 +233,7 @@ inline size_t lds_bytes2(int n, int m) {
 // (kPlans index) on `stream`.
 hipError_t launch_apply_h(int plan, const KArgs& a, hipStream_t stream);
 hipError_t launch_run(int plan, const KArgs& a, hipStream_t stream);  // propagate / adjoint
+hipError_t launch_split(int plan, const KArgs& a, hipStream_t stream);  // diabatic split-operator
 hipError_t launch_diag(int plan, const KArgs& a, hipStream_t stream);
 hipError_t launch_inner(int plan, const KArgs& a, hipStream_t stream);
 hipError_t configure_kernels(int m_max);

@@ -301,9 +301,12 @@ struct Eng {
   // Fused last forward pass (radix RF, Ns = N/RF), momentum multiply and first
   // inverse pass (radix RF, Ns = 1): butterfly j's forward outputs are the k-space
   // points j + r N/RF, exactly the inputs of the inverse butterfly j.
-  template <class Next>
+  // KEXP: multiply by exp(-i ktau p_k^2) / N (the kinetic factor of a split-operator
+  // step, ktau = tau / 2m) instead of p_k / N
+  template <bool KEXP = false, class Next>
   static __device__ __forceinline__ void fused_kspace(const GQD_L cplx* src, GQD_L cplx* dst,
-                                                      const TwS<RF, N / RF>& tw, const Ctx& c, Next&& next) {
+                                                      const TwS<RF, N / RF>& tw, const Ctx& c, Next&& next,
+                                                      double ktau = 0.0) {
     constexpr int NB = 2 * N / RF;
     static_assert(NB % T == 0, "fused pass butterflies");
     constexpr int PER = NB / T;
@@ -331,7 +334,14 @@ struct Eng {
       for (int r = 0; r < RF; ++r) {
         const int kk = j + r * Ns;                      // k-space index
         const int kp = (kk < N / 2) ? kk : kk - N;      // signed wavenumber
-        x[q][r] = cscale(x[q][r], scale * (double)kp);  // p_k / N
+        if constexpr (KEXP) {
+          const double pk = scale * (double)N * (double)kp;
+          double sn, cs;
+          sincos(-ktau * pk * pk, &sn, &cs);
+          x[q][r] = cscale(cmul(x[q][r], mk(cs, sn)), 1.0 / (double)N);
+        } else {
+          x[q][r] = cscale(x[q][r], scale * (double)kp);  // p_k / N
+        }
       }
       DFT<RF, +1>::run(x[q]);
 #pragma unroll
@@ -341,8 +351,10 @@ struct Eng {
     __syncthreads();
   }
 
-  // u = p x on both surfaces (forward DFT, multiply by p_k, inverse DFT / N).
-  static __device__ void kinetic(const OV& x, OV& u, const Ctx& c) {
+  // u = p x on both surfaces (forward DFT, multiply by p_k, inverse DFT / N); with
+  // KEXP, u = exp(-i ktau p^2) x instead (the kinetic factor of a split-operator step).
+  template <bool KEXP = false>
+  static __device__ void kinetic(const OV& x, OV& u, const Ctx& c, double ktau = 0.0) {
     GQD_L cplx* b0 = c.fft;
     GQD_L cplx* b1 = kPP ? c.fft + 2 * N : c.fft;
     constexpr int PL = (R3 == 1) ? 3 : 5;  // table index of the last pass
@@ -364,7 +376,7 @@ struct Eng {
       TwS<RF, N / RF> tf;
       TwS<R1, R2> t2;
       pass<R1, R0, -1, true>(b0, b1, t0, [&] { tw_load<RF, N / RF, 1>(tf, opaque(c.tw)); });
-      fused_kspace(b1, b0, tf, c, [&] { tw_load<R1, R2, 2>(t2, opaque(c.tw)); });
+      fused_kspace<KEXP>(b1, b0, tf, c, [&] { tw_load<R1, R2, 2>(t2, opaque(c.tw)); }, ktau);
       pass<R1, R2, +1, true>(b0, b1, t2, [&] { tw_load<R0, T, PL>(tl, opaque(c.tw)); });
     } else {
       TwS<R2, R0 * R1> t1;
@@ -373,7 +385,7 @@ struct Eng {
       TwS<R1, R3 * R2> t4;
       pass<R1, R0, -1, true>(b0, b1, t0, [&] { tw_load<R2, R0 * R1, 1>(t1, opaque(c.tw)); });
       pass<R2, R0 * R1, -1>(b1, b0, t1, [&] { tw_load<RF, N / RF, 2>(tf, opaque(c.tw)); });
-      fused_kspace(b0, b1, tf, c, [&] { tw_load<R2, R3, 3>(t3, opaque(c.tw)); });
+      fused_kspace<KEXP>(b0, b1, tf, c, [&] { tw_load<R2, R3, 3>(t3, opaque(c.tw)); }, ktau);
       pass<R2, R3, +1, true>(b1, b0, t3, [&] { tw_load<R1, R3 * R2, 4>(t4, opaque(c.tw)); });
       pass<R1, R3 * R2, +1>(b0, b1, t4, [&] { tw_load<R0, T, PL>(tl, opaque(c.tw)); });
     }
@@ -423,6 +435,30 @@ struct Eng {
 #pragma unroll
       for (int r = 0; r < R0; ++r)
         y.v[s][r] = cadd(cscale(y.v[s][r], c.inv2m), cscale(xq[s * N + pt(r)], V[s * N + pt(r)]));
+  }
+
+  // y <- exp(-i W tau) y on owned points for the diabatic matrix W = [[W11, W12],
+  // [W12, W22]] held as V = (W11, W22), F = W12: with W = wbar 1 + dz sz + W12 sx and
+  // r = (dz^2 + W12^2)^(1/2), exp(-i W tau) = exp(-i wbar tau) [cos(r tau) 1
+  // - i sin(r tau) / r (dz sz + W12 sx)].
+  static __device__ __forceinline__ void expW(OV& y, double tau, const Ctx& c) {
+    const GQD_G double* V = opaque(c.V);
+    const GQD_G double* F = opaque(c.F);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const double w11 = V[pt(r)], w22 = V[N + pt(r)], w12 = F[pt(r)];
+      const double wbar = 0.5 * (w11 + w22), dz = 0.5 * (w11 - w22);
+      const double rr = sqrt(dz * dz + w12 * w12);
+      double sr, cr, sb, cb;
+      sincos(rr * tau, &sr, &cr);
+      sincos(-wbar * tau, &sb, &cb);
+      const double sinc = rr > 0.0 ? sr / rr : tau;
+      const cplx a = mk(cr, -sinc * dz), d = mk(cr, sinc * dz), b = mk(0.0, -sinc * w12);
+      const cplx y0 = y.v[0][r], y1 = y.v[1][r];
+      const cplx phase = mk(cb, sb);
+      y.v[0][r] = cmul(phase, cadd(cmul(a, y0), cmul(b, y1)));
+      y.v[1][r] = cmul(phase, cadd(cmul(b, y0), cmul(d, y1)));
+    }
   }
 
   // y += -i F x on owned points (x read from a global vector)
@@ -1081,6 +1117,48 @@ __global__ void __launch_bounds__(Eng<P>::T) k_apply_h(KArgs a) {
   E::store(y, (cplx*)a.aux + im.off);
 }
 
+// Split-operator propagation in the DIABATIC representation (Table I's second-order
+// splitting, composed like the implicit methods): W = [[W11, W12], [W12, W22]] is
+// read from V = (W11, W22) and F = W12.  Each substep of length tau applies
+// exp(-i W tau/2) pointwise, exp(-i T tau) through one transform pair with the phase
+// exp(-i tau p_k^2 / 2m) in k-space, and exp(-i W tau/2) again.  The state stays in
+// registers for the whole call; only the potential is read per substep.
+template <int P>
+__global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(Eng<P>::WPE))) k_split(KArgs a) {
+  using E = Eng<P>;
+  if ((int)blockIdx.x >= a.nlist) return;
+  extern __shared__ double2 smem_raw[];
+  GQD_L cplx* smem = (GQD_L cplx*)smem_raw;
+  const int item = a.list[blockIdx.x];
+  const ItemMeta im = a.items[item];
+  const auto c = E::make_ctx(smem, 0, a, im);
+  cplx* psi = (cplx*)a.psi + im.off;
+  const double dt = a.dt_item ? uniform_d(a.dt_item[item]) : a.dt;
+  const long long nsteps = a.nsteps_item ? a.nsteps_item[item] : a.nsteps;
+  typename E::OV y, t;
+  E::load(y, psi);
+  for (long long n = 0; n < nsteps; ++n) {
+    for (int cc = 0; cc < a.gt.count; ++cc) {
+      const double tau = substep_tau(cc, a.gt) * dt;
+      E::expW(y, 0.5 * tau, c);
+      t = y;
+      E::template kinetic<true>(t, y, c, tau * c.inv2m);
+      E::expW(y, 0.5 * tau, c);
+    }
+  }
+  E::store(y, psi);
+  if (threadIdx.x == 0 && a.stats) {  // no H applications and no solves
+    ItemStats* st = a.stats + item;
+    st->h_applies = 0;
+    st->iterations = 0;
+    st->iterations_sq = 0;
+    st->solves = 0;
+    st->max_iters = 0;
+    st->failures = 0;
+    st->nonfinite = 0;
+  }
+}
+
 // out[item] = (norm, energy, P1, P2); energy = ||A psi||^2 / (2m) + <psi|V psi>
 template <int P>
 __global__ void __launch_bounds__(Eng<P>::T) k_diag(KArgs a) {
@@ -1172,6 +1250,7 @@ static hipError_t set_lds_limit(size_t bytes) {
   if ((e = hipFuncSetAttribute((const void*)k_apply_h<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_run<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_diag<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_split<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_inner<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
@@ -1198,6 +1277,7 @@ hipError_t configure_kernels(int m_max) {
 hipError_t launch_apply_h(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_apply_h, 0) }
 hipError_t launch_run(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_run, a.sc.m) }
 hipError_t launch_diag(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_diag, 0) }
+hipError_t launch_split(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_split, 0) }
 hipError_t launch_inner(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_inner, 0) }
 
 }  // namespace gqd

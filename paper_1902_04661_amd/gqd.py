@@ -21,9 +21,11 @@ TRAP, MIDP = 0, 1
 # the paper's elementary, non-geometric methods (Eqs. 13, 14, 16): order 1, 1 and 2,
 # not composed, 1D only
 EULER_EXPLICIT, EULER_IMPLICIT, SOD = 2, 3, 4
+# the diabatic split-operator method (Table I): the surfaces are read as W11, W22, W12
+SPLIT_OPERATOR = 5
 TRIPLE_JUMP, SUZUKI = 0, 1
 _METHODS = {"trap": TRAP, "midp": MIDP, "euler_explicit": EULER_EXPLICIT,
-            "euler_implicit": EULER_IMPLICIT, "sod": SOD}
+            "euler_implicit": EULER_IMPLICIT, "sod": SOD, "split_operator": SPLIT_OPERATOR}
 _METHODS.update({v: v for v in list(_METHODS.values())})
 _SCHEMES = {"triple_jump": TRIPLE_JUMP, "suzuki": SUZUKI, TRIPLE_JUMP: TRIPLE_JUMP, SUZUKI: SUZUKI}
 SIZES = (256, 512, 1024, 2048, 4096)
