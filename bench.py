@@ -46,9 +46,9 @@ TOL = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "c3e56076b59b965a8d61ce6f104747cccaf3ac7467a31e2e98d87534b64364a0",
-    "fetch_kib": 109210476.125, "fetch_scale": 2.0,
-    "write_kib": 57014379.375, "write_scale": 1.0,
+    "sources_sha256": "6dd9e685e2dd03aa2ccb45fd940858c87cdd038a1c6d4da90ee6b43bf1eba362",
+    "fetch_kib": 109310063.1875, "fetch_scale": 2.0,
+    "write_kib": 57013035.125, "write_scale": 1.0,
     "alg_bytes_same_launch": 331987550208.0,
     "summary": "profiles/k_run_2048_sz8_x1024.md",
 }
@@ -127,6 +127,36 @@ def elementary_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
             "us_per_h_apply_per_packet": 1e6 * el * 256 / (batch * (steps + 1)),
             "alg_GBps": 128.0 * gps / 1e9, "hbm_frac": 128.0 * gps / 1e9 / HBM_PEAK_GBS,
             "workload": f"second-order differencing, {batch} x N={N} packet, dt={SOD_DT}, {steps} steps"}
+
+
+def split_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
+    """The two-state crossing model in both representations, `batch` copies of N = 2048,
+    8th-order Suzuki at dt = 10 a.u.: the diabatic split-operator method (Table I; no
+    linear solves, the state stays in registers) against the adiabatic implicit
+    midpoint on the surfaces and coupling that Eqs. (24-28) give for the same model."""
+    import torch
+    from paper_1902_04661_amd import diabatic
+    d = inputs.diabatic_crossing_item(N)
+    ad, _ = diabatic.adiabatic_item(d)
+    out = {"workload": f"diabatic crossing model, {batch} x N={N}, Suzuki order {ORDER}, dt={DT_STAR}"}
+    s = torch.cuda.current_stream()
+    for name, item, method, nsteps in (("split_operator", diabatic.diabatic_as_surfaces(d), "split_operator", steps),
+                                       ("adiabatic_midpoint", ad, METHOD, 1)):
+        prop = gqd.from_items([item] * batch, device=dev)
+        psi = prop.pack([item.psi0] * batch)
+        opts = gqd.SolverOpts(tol=TOL, restart=32)
+        prop.propagate(psi, method, SCHEME, ORDER, DT_STAR, 1, opts, stats=False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        prop.propagate(psi, method, SCHEME, ORDER, DT_STAR, nsteps, opts, stats=False)
+        e1.record(s)
+        torch.cuda.synchronize()
+        el = e0.elapsed_time(e1) * 1e-3
+        out[name] = {"value": batch * N * nsteps / el, "unit": "grid-point·steps/s",
+                     "ms_per_step": 1e3 * el / nsteps}
+    out["split_over_adiabatic"] = out["split_operator"]["value"] / out["adiabatic_midpoint"]["value"]
+    return out
 
 
 def twod_leg(gqd, inputs, dev, steps: int) -> dict:
@@ -246,6 +276,7 @@ def main(argv=None):
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--twod-steps", type=int, default=100)
     ap.add_argument("--sod-steps", type=int, default=400, help="elementary-method leg (0: skip)")
+    ap.add_argument("--split-steps", type=int, default=8, help="diabatic split-operator leg (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default transform plans")
     ap.add_argument("--adjoint2d-steps", type=int, default=400)
     ap.add_argument("--no-cpu", action="store_true")
@@ -351,6 +382,12 @@ def main(argv=None):
         elementary = elementary_leg(gqd, inputs, dev, args.batch, args.sod_steps)
         print(f"[bench] second-order differencing: {elementary['value']:.3e} gp.steps/s "
               f"({100 * elementary['hbm_frac']:.0f} % of HBM peak)", file=sys.stderr, flush=True)
+    split = {}
+    if args.split_steps > 0:
+        split = split_leg(gqd, inputs, dev, args.batch, args.split_steps)
+        print(f"[bench] split operator: {split['split_operator']['value']:.3e} gp.steps/s, "
+              f"{split['split_over_adiabatic']:.1f}x the adiabatic midpoint on the same model",
+              file=sys.stderr, flush=True)
     twod = {}
     if args.twod_steps > 0:
         twod = twod_leg(gqd, inputs, dev, args.twod_steps)
@@ -400,6 +437,7 @@ def main(argv=None):
         "two_dim": twod,
         "adjoint_2d": adjoint2d,
         "elementary": elementary,
+        "split_operator": split,
         # the batched and the differentiated forms against the plain one-packet solve, all
         # at the same tolerance and step
         "comparisons": {

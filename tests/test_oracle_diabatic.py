@@ -118,3 +118,18 @@ def test_adiabatic_and_diabatic_propagations_agree_at_the_composition_order():
     upper = it.dq * np.sum(np.abs(ad[0]) ** 2)
     assert upper > 0.03  # population crossed to the upper adiabatic surface
     assert diffs[1] < 1e-6 and 40.0 < diffs[0] / diffs[1] < 90.0  # sixth order: 64
+
+
+def test_library_transform_matches_the_oracle():
+    # paper_1902_04661_amd.diabatic is written apart from the oracle; pin it to it
+    from paper_1902_04661_amd import diabatic as D
+    it = I.diabatic_crossing_item(1024)
+    V, F12, c, s = O.diabatic_to_adiabatic(it.W, it.dW)
+    V2, F2, theta = D.adiabatic_surfaces(it.W, it.dW)
+    scale = np.abs(V).max()
+    assert np.abs(V - V2).max() < 1e-15 * scale
+    assert np.abs(F12 - F2).max() < 1e-13 * np.abs(F12).max()
+    assert np.abs(np.cos(theta) - c).max() < 1e-15 and np.abs(np.sin(theta) - s).max() < 1e-15
+    ad, th = D.adiabatic_item(it)
+    assert np.abs(ad.psi0 - O.to_adiabatic(it.psi0, c, s)).max() < 1e-15
+    assert np.abs(D.rotate(ad.psi0, th, inverse=True) - it.psi0).max() < 1e-15
