@@ -51,6 +51,11 @@ def test_invalid_arguments_fail_without_a_gpu():
     mass = (ctypes.c_double * 1)(1.0)
     desc = gqd._GridDesc(1, 2, 1, n, qmin, qmax, mass)
     assert lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)) == -5   # unsupported size
+    n[0] = 256
+    desc = gqd._GridDesc(1, 2, 0, n, qmin, qmax, mass)
+    assert lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)) == -1   # empty batch
+    assert b"batch" in lib.gqd_last_error()
+    n[0] = 300
     desc = gqd._GridDesc(3, 2, 1, n, qmin, qmax, mass)
     assert lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)) == -5   # dims
     # 2D: n x n with n in {64, 128, 256, 512}, two masses
