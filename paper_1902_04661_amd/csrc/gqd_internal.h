@@ -98,6 +98,10 @@ struct KArgs {
 struct Plan {
   int N, R0, R1, R2, R3;
   bool two_buf;
+  // four-step form (N = R0 * 512, 2 R0 waves, R1 = R2 = R3 = 8): the radix-R0 stage on
+  // owned points, one exchange through LDS, then one 512-point transform per wave in
+  // the wave's own LDS region; two workgroup barriers per application instead of six
+  bool four_step = false;
 };
 constexpr int kNumPlans = 11;
 constexpr Plan kPlans[kNumPlans] = {
@@ -108,7 +112,7 @@ constexpr Plan kPlans[kNumPlans] = {
     {1024, 4, 8, 8, 4, true},    // 4
     {1024, 8, 8, 4, 4, true},    // 5
     {1024, 8, 8, 16, 1, true},   // 6
-    {2048, 4, 8, 8, 8, true},    // 7
+    {2048, 4, 8, 8, 8, true, true},  // 7
     {2048, 8, 8, 8, 4, true},    // 8
     {2048, 8, 16, 16, 1, true},  // 9
     {4096, 8, 8, 8, 8, false},   // 10
@@ -129,7 +133,13 @@ struct PassNR {
 constexpr int twiddle_passes(int plan, PassNR* out) {
   const int R0 = kPlans[plan].R0, R1 = kPlans[plan].R1, R2 = kPlans[plan].R2, R3 = kPlans[plan].R3;
   int n = 0;
-  if (R3 == 1) {
+  if (kPlans[plan].four_step) {
+    // the outer twiddles exp(-2 pi i t k1 / N) (t < N/R0, k1 < R0), then the two
+    // twiddled radix-8 passes of a 512-point transform; the inverse conjugates them
+    out[n++] = PassNR{kPlans[plan].N / R0, R0};
+    out[n++] = PassNR{8, 8};
+    out[n++] = PassNR{64, 8};
+  } else if (R3 == 1) {
     out[n++] = PassNR{R0, R1};            // forward
     out[n++] = PassNR{R0 * R1, R2};       // forward, fused with the first inverse pass
     out[n++] = PassNR{R2, R1};            // inverse

@@ -23,6 +23,9 @@ struct Eng {
   // operator input kept in registers; in-place classes: one buffer, the input re-read
   // and the partial H result parked in the workspace
   static constexpr bool kPP = kPlans[PLAN].two_buf;
+  static constexpr bool kFS = kPlans[PLAN].four_step;
+  static_assert(!kFS || (N == R0 * 512 && W == 2 * R0 && R1 == 8 && R2 == 8 && R3 == 8 && kPP),
+                "four-step plans: one 512-point sub-transform per wave, two LDS buffers");
   // waves per SIMD the register allocation must leave room for.  Plans whose threads
   // own R0 <= 4 points per surface are held to 256 VGPRs (two waves per SIMD): with
   // the Gram-Schmidt loads issued in bursts the allocator would otherwise spill into
@@ -351,10 +354,184 @@ struct Eng {
     __syncthreads();
   }
 
+  // ---------------------------------------------------------- four-step transform
+  // N = R0 * 512 points, n = 512 n1 + n2 and k = k1 + R0 k2 (n1, k1 < R0; n2, k2 < 512):
+  //   X[k1 + R0 k2] = sum_n2 w_512^(n2 k2) w_N^(n2 k1) sum_n1 x[512 n1 + n2] w_R0^(n1 k1).
+  // Thread t = n2 owns x[512 n1 + t]: the inner sums are a radix-R0 DFT in registers.
+  // After one exchange wave (s, k1) holds the 512 values of its (surface, k1) slab and
+  // runs the outer sum as three radix-8 Stockham passes in its own 512-element LDS
+  // region; the last leaves X[k1 + R0 (j + 64 r)] in lane j's register r, where the
+  // k-space factor is applied and the inverse's first pass starts.  The inverse runs
+  // the same steps backwards (conjugate twiddles) and returns through one exchange to
+  // owned points.  Only the two exchanges need workgroup barriers; the passes inside a
+  // wave are ordered by wave-level synchronisation.
+  static __device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // twiddles of a radix-8 pass with stride Ns (table P) for butterfly j = lane
+  template <int Ns, int P>
+  static __device__ __forceinline__ void fs_tw(cplx (&w)[7], const GQD_G cplx* tw) {
+    constexpr int OFF = pass_table_offset(PLAN, P);
+    const GQD_G cplx* tk = tw + OFF + ((lane_tid() & 63) % Ns) * 7;
+#pragma unroll
+    for (int r = 0; r < 7; ++r) w[r] = tk[r];
+  }
+  // one radix-8 pass of the wave's 512-point transform: x[r] = element j + 64 r on entry
+  template <int S>
+  static __device__ __forceinline__ void fs_bfly(cplx (&x)[8], const cplx (&w)[7]) {
+#pragma unroll
+    for (int r = 1; r < 8; ++r) x[r] = twmul<S>(x[r], w[r - 1]);
+    DFT<8, S>::run(x);
+  }
+  template <bool KEXP = false>
+  static __device__ void kinetic_fs(const OV& x, OV& u, const Ctx& c, double ktau) {
+    GQD_L cplx* b0 = c.fft;          // forward exchange: slab (s, k1) at (s R0 + k1) * 512
+    GQD_L cplx* b1 = c.fft + 2 * N;  // wave regions; the inverse exchange uses the same slabs
+    constexpr int OFF0 = pass_table_offset(PLAN, 0);
+    // inner radix-R0 DFT on owned points, outer twiddle w_N^(t k1), exchange
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      cplx y[R0];
+#pragma unroll
+      for (int r = 0; r < R0; ++r) y[r] = x.v[s][r];
+      DFT<R0, -1>::run(y);
+      const GQD_G cplx* tk = opaque(c.tw) + OFF0 + lane_tid() * (R0 - 1);
+#pragma unroll
+      for (int k1 = 1; k1 < R0; ++k1) y[k1] = cmul(y[k1], tk[k1 - 1]);
+      const int t = lane_tid();
+#pragma unroll
+      for (int k1 = 0; k1 < R0; ++k1) b0[(s * R0 + k1) * 512 + t] = y[k1];
+    }
+    __syncthreads();
+    // wave (s, k1): its slab and its region; the lane index is re-derived at each use so
+    // that address arithmetic stays local
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int k1 = wv % R0;
+    GQD_L cplx* reg = b1 + wv * 512;
+    const GQD_L cplx* slab = b0 + wv * 512;
+    cplx v[8], w[7];
+    // forward pass Ns = 1 (no twiddles), straight from the slab
+    {
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = slab[j + 64 * r];
+    }
+    fs_tw<8, 1>(w, opaque(c.tw));
+    DFT<8, -1>::run(v);
+    {
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) reg[swz(j * 8 + r)] = v[r];
+    }
+    wave_sync();
+    // forward pass Ns = 8
+    {
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = reg[swz(j + 64 * r)];
+    }
+    fs_bfly<-1>(v, w);
+    fs_tw<64, 2>(w, opaque(c.tw));
+    {
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) reg[(j >> 3) * 64 + (j & 7) + 8 * r] = v[r];
+    }
+    wave_sync();
+    // forward pass Ns = 64: v[r] = X[k1 + R0 (j + 64 r)]
+    {
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = reg[j + 64 * r];
+    }
+    fs_bfly<-1>(v, w);
+    fs_tw<8, 1>(w, opaque(c.tw));
+    {
+      const double scale = opaque_d(c.pscale) / (double)N;
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int kk = k1 + R0 * (j + 64 * r);
+        const int kp = (kk < N / 2) ? kk : kk - N;
+        if constexpr (KEXP) {
+          const double pk = scale * (double)N * (double)kp;
+          double sn, cs;
+          sincos(-ktau * pk * pk, &sn, &cs);
+          v[r] = cscale(cmul(v[r], mk(cs, sn)), 1.0 / (double)N);
+        } else {
+          v[r] = cscale(v[r], scale * (double)kp);  // p_k / N
+        }
+      }
+    }
+    // inverse pass Ns = 1 on the registers
+    DFT<8, +1>::run(v);
+    {
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) reg[swz(j * 8 + r)] = v[r];
+    }
+    wave_sync();
+    // inverse pass Ns = 8
+    {
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = reg[swz(j + 64 * r)];
+    }
+    fs_bfly<+1>(v, w);
+    fs_tw<64, 2>(w, opaque(c.tw));
+    {
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) reg[(j >> 3) * 64 + (j & 7) + 8 * r] = v[r];
+    }
+    wave_sync();
+    // inverse pass Ns = 64, then the outer twiddle w_N^(-n2 k1), n2 = j + 64 r, into the slab
+    {
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = reg[j + 64 * r];
+    }
+    fs_bfly<+1>(v, w);
+    if (k1 != 0) {
+      const GQD_G cplx* tk = opaque(c.tw) + OFF0 + (lane_tid() & 63) * (R0 - 1) + k1 - 1;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = twmul<+1>(v[r], tk[64 * r * (R0 - 1)]);
+    }
+    {
+      const int j = lane_tid() & 63;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) reg[j + 64 * r] = v[r];
+    }
+    __syncthreads();
+    // inverse radix-R0 DFT over k1 back to owned points
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      cplx y[R0];
+      const int t = lane_tid();
+#pragma unroll
+      for (int q = 0; q < R0; ++q) y[q] = b1[(s * R0 + q) * 512 + t];
+      DFT<R0, +1>::run(y);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) u.v[s][r] = y[r];
+    }
+  }
+
   // u = p x on both surfaces (forward DFT, multiply by p_k, inverse DFT / N); with
   // KEXP, u = exp(-i ktau p^2) x instead (the kinetic factor of a split-operator step).
   template <bool KEXP = false>
   static __device__ void kinetic(const OV& x, OV& u, const Ctx& c, double ktau = 0.0) {
+    if constexpr (kFS) {
+      kinetic_fs<KEXP>(x, u, c, ktau);
+    } else {
+      kinetic_sh<KEXP>(x, u, c, ktau);
+    }
+  }
+
+  // Stockham form: every pass over the whole transform, one barrier each
+  template <bool KEXP = false>
+  static __device__ void kinetic_sh(const OV& x, OV& u, const Ctx& c, double ktau = 0.0) {
     GQD_L cplx* b0 = c.fft;
     GQD_L cplx* b1 = kPP ? c.fft + 2 * N : c.fft;
     constexpr int PL = (R3 == 1) ? 3 : 5;  // table index of the last pass
