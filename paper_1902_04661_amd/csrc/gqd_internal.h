@@ -98,24 +98,24 @@ struct KArgs {
 struct Plan {
   int N, R0, R1, R2, R3;
   bool two_buf;
-  // four-step form (N = R0 * 512, 2 R0 waves, R1 = R2 = R3 = 8): the radix-R0 stage on
-  // owned points, one exchange through LDS, then one 512-point transform per wave in
-  // the wave's own LDS region; two workgroup barriers per application instead of six
+  // four-step form: the radix-R0 stage on owned points, one exchange through LDS, then
+  // the (N/R0)-point transforms of the 2 R0 (surface, k1) slabs, each inside one wave's
+  // own LDS region (radices R1, R2, R3); workgroup barriers only around the exchanges
   bool four_step = false;
 };
 constexpr int kNumPlans = 11;
 constexpr Plan kPlans[kNumPlans] = {
-    {256, 4, 8, 8, 1, true},     // 0
+    {256, 4, 8, 8, 1, true, true},     // 0
     {256, 4, 4, 4, 4, true},     // 1
-    {512, 4, 8, 4, 4, true},     // 2
+    {512, 4, 8, 4, 4, true, true},     // 2
     {512, 8, 8, 8, 1, true},     // 3
-    {1024, 4, 8, 8, 4, true},    // 4
+    {1024, 4, 8, 8, 4, true, true},    // 4
     {1024, 8, 8, 4, 4, true},    // 5
     {1024, 8, 8, 16, 1, true},   // 6
     {2048, 4, 8, 8, 8, true, true},  // 7
     {2048, 8, 8, 8, 4, true},    // 8
     {2048, 8, 16, 16, 1, true},  // 9
-    {4096, 8, 8, 8, 8, false},   // 10
+    {4096, 8, 8, 8, 8, false, true},   // 10
 };
 constexpr int kMaxPlansPerClass = 3;
 // plans of each size class, default first; -1 ends a list
@@ -134,11 +134,18 @@ constexpr int twiddle_passes(int plan, PassNR* out) {
   const int R0 = kPlans[plan].R0, R1 = kPlans[plan].R1, R2 = kPlans[plan].R2, R3 = kPlans[plan].R3;
   int n = 0;
   if (kPlans[plan].four_step) {
-    // the outer twiddles exp(-2 pi i t k1 / N) (t < N/R0, k1 < R0), then the two
-    // twiddled radix-8 passes of a 512-point transform; the inverse conjugates them
+    // the outer twiddles exp(-2 pi i t k1 / N) (t < N/R0, k1 < R0), then the twiddled
+    // passes of the slab transform (forward, the fused one included, then inverse)
     out[n++] = PassNR{kPlans[plan].N / R0, R0};
-    out[n++] = PassNR{8, 8};
-    out[n++] = PassNR{64, 8};
+    if (R3 == 1) {
+      out[n++] = PassNR{R1, R2};  // fused
+      out[n++] = PassNR{R2, R1};
+    } else {
+      out[n++] = PassNR{R1, R2};
+      out[n++] = PassNR{R1 * R2, R3};  // fused
+      out[n++] = PassNR{R3, R2};
+      out[n++] = PassNR{R3 * R2, R1};
+    }
   } else if (R3 == 1) {
     out[n++] = PassNR{R0, R1};            // forward
     out[n++] = PassNR{R0 * R1, R2};       // forward, fused with the first inverse pass

@@ -24,8 +24,10 @@ struct Eng {
   // and the partial H result parked in the workspace
   static constexpr bool kPP = kPlans[PLAN].two_buf;
   static constexpr bool kFS = kPlans[PLAN].four_step;
-  static_assert(!kFS || (N == R0 * 512 && W == 2 * R0 && R1 == 8 && R2 == 8 && R3 == 8 && kPP),
-                "four-step plans: one 512-point sub-transform per wave, two LDS buffers");
+  // four-step form: slabs of M = N / R0 points, 2 R0 of them, SPW per wave
+  static constexpr int M = N / R0;
+  static constexpr int SPW = (2 * R0) / W;
+  static_assert(!kFS || SPW * W == 2 * R0, "four-step plans: whole slabs per wave");
   // waves per SIMD the register allocation must leave room for.  Plans whose threads
   // own R0 <= 4 points per surface are held to 256 VGPRs (two waves per SIMD): with
   // the Gram-Schmidt loads issued in bursts the allocator would otherwise spill into
@@ -355,41 +357,158 @@ struct Eng {
   }
 
   // ---------------------------------------------------------- four-step transform
-  // N = R0 * 512 points, n = 512 n1 + n2 and k = k1 + R0 k2 (n1, k1 < R0; n2, k2 < 512):
-  //   X[k1 + R0 k2] = sum_n2 w_512^(n2 k2) w_N^(n2 k1) sum_n1 x[512 n1 + n2] w_R0^(n1 k1).
-  // Thread t = n2 owns x[512 n1 + t]: the inner sums are a radix-R0 DFT in registers.
-  // After one exchange wave (s, k1) holds the 512 values of its (surface, k1) slab and
-  // runs the outer sum as three radix-8 Stockham passes in its own 512-element LDS
-  // region; the last leaves X[k1 + R0 (j + 64 r)] in lane j's register r, where the
-  // k-space factor is applied and the inverse's first pass starts.  The inverse runs
-  // the same steps backwards (conjugate twiddles) and returns through one exchange to
-  // owned points.  Only the two exchanges need workgroup barriers; the passes inside a
-  // wave are ordered by wave-level synchronisation.
+  // n = M n1 + n2 and k = k1 + R0 k2 (n1, k1 < R0; n2, k2 < M = N / R0):
+  //   X[k1 + R0 k2] = sum_n2 w_M^(n2 k2) w_N^(n2 k1) sum_n1 x[M n1 + n2] w_R0^(n1 k1).
+  // Thread t = n2 owns x[M n1 + t]: the inner sums are a radix-R0 DFT in registers.
+  // One exchange writes the (surface s, k1) slab q = s R0 + k1 at q M; wave w then owns
+  // slabs w SPW ... w SPW + SPW - 1 and runs the outer sums as a Stockham transform of M
+  // points (radices R1, R2, R3) in its own region, the k-space factor inside the fused
+  // pass as in the whole-transform form.  The inverse ends with the outer twiddle
+  // w_N^(-n2 k1) and returns through one exchange to owned points.  Passes inside a wave
+  // are ordered by wave-level synchronisation; only the exchanges need workgroup
+  // barriers.  Two-buffer plans exchange forward through b0 and work and exchange back
+  // in b1; in-place plans do all of it in b0 (and end with a barrier, as the next
+  // application's exchange overwrites it).
   static __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  // twiddles of a radix-8 pass with stride Ns (table P) for butterfly j = lane
-  template <int Ns, int P>
-  static __device__ __forceinline__ void fs_tw(cplx (&w)[7], const GQD_G cplx* tw) {
-    constexpr int OFF = pass_table_offset(PLAN, P);
-    const GQD_G cplx* tk = tw + OFF + ((lane_tid() & 63) % Ns) * 7;
+  // One Stockham pass of radix R (stride Ns, sign S) over the wave's slabs: butterfly
+  // b = lane + 64 q is butterfly j = b mod (M/R) of slab e = b / (M/R); it reads
+  // x[e M + j + r M/R], twiddles by table TP (none for TP < 0), applies the DFT and writes
+  // y[e M + (j/Ns) Ns R + j mod Ns + r Ns].  All of the wave's loads come before its
+  // stores, so src may equal dst.  SWIN / SWOUT route the input / output index through
+  // swz; OUTER multiplies output n2 = j + r M/R by conj(w_N^(n2 k1)) of the slab's k1.
+  template <int R, int Ns, int S, int TP, bool SWIN, bool SWOUT, bool OUTER>
+  static __device__ __forceinline__ void wpass(const GQD_L cplx* src, GQD_L cplx* dst, const Ctx& c,
+                                               int slab0) {
+    constexpr int NR = M / R;
+    constexpr int NB = SPW * NR;
+    static_assert(NB % 64 == 0, "whole butterflies per lane");
+    constexpr int PER = NB / 64;
+    cplx x[PER][R];
+    {
+      const int l = lane_tid() & 63;
 #pragma unroll
-    for (int r = 0; r < 7; ++r) w[r] = tk[r];
+      for (int q = 0; q < PER; ++q) {
+        const int b = l + 64 * q, e = b / NR, j = b % NR;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = e * M + j + r * NR;
+          x[q][r] = src[SWIN ? swz(i) : i];
+        }
+      }
+    }
+    if constexpr (TP >= 0) {
+      const GQD_G cplx* tw = opaque(c.tw) + pass_table_offset(PLAN, TP);
+      const int l = lane_tid() & 63;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int k = ((l + 64 * q) % NR) % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) x[q][r] = twmul<S>(x[q][r], tw[k * (R - 1) + r - 1]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) DFT<R, S>::run(x[q]);
+    if constexpr (OUTER) {
+      const GQD_G cplx* tw0 = opaque(c.tw) + pass_table_offset(PLAN, 0);
+      const int l = lane_tid() & 63;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int b = l + 64 * q, e = b / NR, j = b % NR;
+        const int k1 = (slab0 + e) % R0;
+        if (k1 != 0) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) x[q][r] = twmul<+1>(x[q][r], tw0[(j + r * NR) * (R0 - 1) + k1 - 1]);
+        }
+      }
+    }
+    {
+      const int l = lane_tid() & 63;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int b = l + 64 * q, e = b / NR, j = b % NR;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int o = e * M + (j / Ns) * Ns * R + j % Ns + r * Ns;
+          dst[SWOUT ? swz(o) : o] = x[q][r];
+        }
+      }
+    }
   }
-  // one radix-8 pass of the wave's 512-point transform: x[r] = element j + 64 r on entry
-  template <int S>
-  static __device__ __forceinline__ void fs_bfly(cplx (&x)[8], const cplx (&w)[7]) {
+  // Fused last forward pass (radix RF, Ns = M/RF, table TP), k-space factor and first
+  // inverse pass (radix RF, Ns = 1) over the wave's slabs: forward output r of butterfly
+  // j of slab e is X[k1 + R0 (j + r M/RF)]; the inverse writes y[e M + j RF + r] through swz.
+  template <bool KEXP, int TP, bool SWIN>
+  static __device__ __forceinline__ void wfused(const GQD_L cplx* src, GQD_L cplx* dst, const Ctx& c,
+                                                int slab0, double ktau) {
+    constexpr int NR = M / RF;
+    constexpr int NB = SPW * NR;
+    static_assert(NB % 64 == 0, "whole butterflies per lane");
+    constexpr int PER = NB / 64;
+    cplx x[PER][RF];
+    {
+      const int l = lane_tid() & 63;
 #pragma unroll
-    for (int r = 1; r < 8; ++r) x[r] = twmul<S>(x[r], w[r - 1]);
-    DFT<8, S>::run(x);
+      for (int q = 0; q < PER; ++q) {
+        const int b = l + 64 * q, e = b / NR, j = b % NR;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+          const int i = e * M + j + r * NR;
+          x[q][r] = src[SWIN ? swz(i) : i];
+        }
+      }
+    }
+    {
+      const GQD_G cplx* tw = opaque(c.tw) + pass_table_offset(PLAN, TP);
+      const int l = lane_tid() & 63;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int j = (l + 64 * q) % NR;
+#pragma unroll
+        for (int r = 1; r < RF; ++r) x[q][r] = cmul(x[q][r], tw[j * (RF - 1) + r - 1]);
+      }
+    }
+    const double scale = opaque_d(c.pscale) / (double)N;
+    {
+      const int l = lane_tid() & 63;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int b = l + 64 * q, e = b / NR, j = b % NR;
+        const int k1 = (slab0 + e) % R0;
+        DFT<RF, -1>::run(x[q]);
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+          const int kk = k1 + R0 * (j + r * NR);          // k-space index
+          const int kp = (kk < N / 2) ? kk : kk - N;      // signed wavenumber
+          if constexpr (KEXP) {
+            const double pk = scale * (double)N * (double)kp;
+            double sn, cs;
+            sincos(-ktau * pk * pk, &sn, &cs);
+            x[q][r] = cscale(cmul(x[q][r], mk(cs, sn)), 1.0 / (double)N);
+          } else {
+            x[q][r] = cscale(x[q][r], scale * (double)kp);  // p_k / N
+          }
+        }
+        DFT<RF, +1>::run(x[q]);
+      }
+    }
+    {
+      const int l = lane_tid() & 63;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int b = l + 64 * q, e = b / NR, j = b % NR;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) dst[swz(e * M + j * RF + r)] = x[q][r];
+      }
+    }
   }
   template <bool KEXP = false>
   static __device__ void kinetic_fs(const OV& x, OV& u, const Ctx& c, double ktau) {
-    GQD_L cplx* b0 = c.fft;          // forward exchange: slab (s, k1) at (s R0 + k1) * 512
-    GQD_L cplx* b1 = c.fft + 2 * N;  // wave regions; the inverse exchange uses the same slabs
-    constexpr int OFF0 = pass_table_offset(PLAN, 0);
+    GQD_L cplx* b0 = c.fft;                          // forward exchange
+    GQD_L cplx* b1 = kPP ? c.fft + 2 * N : c.fft;    // slab work and the way back
     // inner radix-R0 DFT on owned points, outer twiddle w_N^(t k1), exchange
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -397,112 +516,33 @@ struct Eng {
 #pragma unroll
       for (int r = 0; r < R0; ++r) y[r] = x.v[s][r];
       DFT<R0, -1>::run(y);
-      const GQD_G cplx* tk = opaque(c.tw) + OFF0 + lane_tid() * (R0 - 1);
+      const GQD_G cplx* tk = opaque(c.tw) + pass_table_offset(PLAN, 0) + lane_tid() * (R0 - 1);
 #pragma unroll
       for (int k1 = 1; k1 < R0; ++k1) y[k1] = cmul(y[k1], tk[k1 - 1]);
       const int t = lane_tid();
 #pragma unroll
-      for (int k1 = 0; k1 < R0; ++k1) b0[(s * R0 + k1) * 512 + t] = y[k1];
+      for (int k1 = 0; k1 < R0; ++k1) b0[(s * R0 + k1) * M + t] = y[k1];
     }
     __syncthreads();
-    // wave (s, k1): its slab and its region; the lane index is re-derived at each use so
-    // that address arithmetic stays local
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int k1 = wv % R0;
-    GQD_L cplx* reg = b1 + wv * 512;
-    const GQD_L cplx* slab = b0 + wv * 512;
-    cplx v[8], w[7];
-    // forward pass Ns = 1 (no twiddles), straight from the slab
-    {
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = slab[j + 64 * r];
-    }
-    fs_tw<8, 1>(w, opaque(c.tw));
-    DFT<8, -1>::run(v);
-    {
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) reg[swz(j * 8 + r)] = v[r];
-    }
-    wave_sync();
-    // forward pass Ns = 8
-    {
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = reg[swz(j + 64 * r)];
-    }
-    fs_bfly<-1>(v, w);
-    fs_tw<64, 2>(w, opaque(c.tw));
-    {
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) reg[(j >> 3) * 64 + (j & 7) + 8 * r] = v[r];
-    }
-    wave_sync();
-    // forward pass Ns = 64: v[r] = X[k1 + R0 (j + 64 r)]
-    {
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = reg[j + 64 * r];
-    }
-    fs_bfly<-1>(v, w);
-    fs_tw<8, 1>(w, opaque(c.tw));
-    {
-      const double scale = opaque_d(c.pscale) / (double)N;
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int kk = k1 + R0 * (j + 64 * r);
-        const int kp = (kk < N / 2) ? kk : kk - N;
-        if constexpr (KEXP) {
-          const double pk = scale * (double)N * (double)kp;
-          double sn, cs;
-          sincos(-ktau * pk * pk, &sn, &cs);
-          v[r] = cscale(cmul(v[r], mk(cs, sn)), 1.0 / (double)N);
-        } else {
-          v[r] = cscale(v[r], scale * (double)kp);  // p_k / N
-        }
-      }
-    }
-    // inverse pass Ns = 1 on the registers
-    DFT<8, +1>::run(v);
-    {
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) reg[swz(j * 8 + r)] = v[r];
-    }
-    wave_sync();
-    // inverse pass Ns = 8
-    {
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = reg[swz(j + 64 * r)];
-    }
-    fs_bfly<+1>(v, w);
-    fs_tw<64, 2>(w, opaque(c.tw));
-    {
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) reg[(j >> 3) * 64 + (j & 7) + 8 * r] = v[r];
-    }
-    wave_sync();
-    // inverse pass Ns = 64, then the outer twiddle w_N^(-n2 k1), n2 = j + 64 r, into the slab
-    {
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = reg[j + 64 * r];
-    }
-    fs_bfly<+1>(v, w);
-    if (k1 != 0) {
-      const GQD_G cplx* tk = opaque(c.tw) + OFF0 + (lane_tid() & 63) * (R0 - 1) + k1 - 1;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = twmul<+1>(v[r], tk[64 * r * (R0 - 1)]);
-    }
-    {
-      const int j = lane_tid() & 63;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) reg[j + 64 * r] = v[r];
+    const int slab0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * SPW;
+    const GQD_L cplx* X = b0 + slab0 * M;
+    GQD_L cplx* Y = b1 + slab0 * M;
+    if constexpr (R3 == 1) {
+      wpass<R1, 1, -1, -1, false, true, false>(X, Y, c, slab0);
+      wave_sync();
+      wfused<KEXP, 1, true>(Y, Y, c, slab0, ktau);
+      wave_sync();
+      wpass<R1, R2, +1, 2, true, false, true>(Y, Y, c, slab0);
+    } else {
+      wpass<R1, 1, -1, -1, false, true, false>(X, Y, c, slab0);
+      wave_sync();
+      wpass<R2, R1, -1, 1, true, false, false>(Y, Y, c, slab0);
+      wave_sync();
+      wfused<KEXP, 2, false>(Y, Y, c, slab0, ktau);
+      wave_sync();
+      wpass<R2, R3, +1, 3, true, false, false>(Y, Y, c, slab0);
+      wave_sync();
+      wpass<R1, R3 * R2, +1, 4, false, false, true>(Y, Y, c, slab0);
     }
     __syncthreads();
     // inverse radix-R0 DFT over k1 back to owned points
@@ -511,11 +551,12 @@ struct Eng {
       cplx y[R0];
       const int t = lane_tid();
 #pragma unroll
-      for (int q = 0; q < R0; ++q) y[q] = b1[(s * R0 + q) * 512 + t];
+      for (int q = 0; q < R0; ++q) y[q] = b1[(s * R0 + q) * M + t];
       DFT<R0, +1>::run(y);
 #pragma unroll
       for (int r = 0; r < R0; ++r) u.v[s][r] = y[r];
     }
+    if constexpr (!kPP) __syncthreads();  // the next application's exchange reuses b0
   }
 
   // u = p x on both surfaces (forward DFT, multiply by p_k, inverse DFT / N); with
