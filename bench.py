@@ -46,9 +46,9 @@ TOL = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "f179f060679715a47a1b19366d6cca6af986ab212a4f59ca1eb27607606d5101",
-    "fetch_kib": 113577377.6875, "fetch_scale": 2.0,
-    "write_kib": 56882107.5, "write_scale": 1.0,
+    "sources_sha256": "639d6b3ea0aed4e0ab062f8b9c868d371c1735171adf7c72d10a70a59fcd379a",
+    "fetch_kib": 112926437.1875, "fetch_scale": 2.0,
+    "write_kib": 56880310.875, "write_scale": 1.0,
     "alg_bytes_same_launch": 330511155200.0,
     "summary": "profiles/k_run_2048_sz8_x1024.md",
 }
