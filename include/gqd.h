@@ -36,7 +36,9 @@
  *   gF   float64 [item][d 2][n][n]
  * so V, F and gF all use the state offsets (in doubles).  A group of workgroups shares
  * each item (cooperative launches); gqd_apply_H and gqd_diag then also need the
- * workspace, gqd_propagate_items is unsupported.  The group crosses grid barriers with
+ * workspace, gqd_propagate_items is unsupported.  gqd_adjoint gives each item two
+ * groups, one for the phi solves and one for the mu solves of every substep, so a 2D
+ * workspace holds two regions per item.  The group crosses grid barriers with
  * a bounded wait: if one ever times out the item stops and a call given a gqd_stats
  * pointer returns GQD_ERR_HIP.
  *

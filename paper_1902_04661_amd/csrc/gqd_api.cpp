@@ -57,6 +57,7 @@ struct gqd_handle {
   unsigned* d_sync = nullptr;
   double* d_part = nullptr;
   int resident_cap = 0;  // workgroups the partial and sync areas are sized for
+  int stats_roles = 1;   // groups per item of the last 2D launch (2: merge their statistics)
   std::vector<ItemMeta> items;
   long long total_complex = 0;
   std::vector<int> class_lists[kNumClasses];
@@ -101,19 +102,22 @@ gqd_status check_opts(const gqd_handle* h, const gqd_solver_opts* o) {
 }
 
 size_t work_need(const gqd_handle* h, int m) {
-  if (h->dims == 2) return (size_t)h->total_complex * (size_t)(kWork2Extra + m + 1) * sizeof(double2);
+  // 2D: two regions per item, as the reverse sweep solves phi and mu on two groups at once
+  if (h->dims == 2) return 2 * (size_t)h->total_complex * (size_t)(kWork2Extra + m + 1) * sizeof(double2);
   return (size_t)h->total_complex * (size_t)(m + kWorkExtra) * sizeof(double2);
 }
 
 constexpr int kSpinLimit = 1 << 22;  // polls of one grid barrier (seconds) before abort
 
-// Launch the 2D kernel over all items: groups of G workgroups per item, as many
-// items per cooperative launch as can be resident together.
+// Launch the 2D kernel over all items: groups of G workgroups per item (two groups per
+// item for the reverse sweep, which solves phi and mu side by side), as many items per
+// cooperative launch as can be resident together.
 gqd_status run2d(gqd_handle* h, K2Args a, hipStream_t stream) {
   int resident = 0;
   GQD_HIP(max_resident2d(h->line_cls, a.sc.m, &resident));
   if (resident < 1) return fail(GQD_ERR_UNSUPPORTED, "2D kernel cannot be resident");
   if (resident > h->resident_cap) resident = h->resident_cap;
+  const int roles = (a.mode == kM2Adjoint && resident >= 2) ? 2 : 1;
   const long long vec = 2LL * h->n2 * h->n2;
   long long gmax = 2LL * (h->n2 / kLineWaves);
   if (vec / kThreads2 < gmax) gmax = vec / kThreads2;
@@ -122,9 +126,15 @@ gqd_status run2d(gqd_handle* h, K2Args a, hipStream_t stream) {
   if (per_item < gmax) gmax = per_item;
   int G = 1;
   while (2LL * G <= gmax) G *= 2;
-  const int per_launch = resident / G;
+  // two groups share what one would have had: every grid barrier writes back and
+  // invalidates the L2 of each XCD it spans, so more workgroups per XCD make each
+  // barrier dearer (at 256 x 256: 128 + 128 workgroups lost to 64 + 64)
+  if (roles == 2 && G > 1) G /= 2;
+  const int per_launch = resident / (G * roles);
   a.G = G;
+  a.roles = roles;
   a.work_stride = (long long)(kWork2Extra + a.sc.m + 1) * vec;
+  h->stats_roles = roles;
   double* out0 = a.out;
   for (int base = 0; base < h->batch; base += per_launch) {
     const int cnt = (h->batch - base < per_launch) ? h->batch - base : per_launch;
@@ -132,8 +142,10 @@ gqd_status run2d(gqd_handle* h, K2Args a, hipStream_t stream) {
     b.items = h->d_items2 + base;
     b.batch = cnt;
     b.stats = h->d_stats + base;
+    b.stats1 = h->d_stats + h->batch + base;
     if (out0) b.out = out0 + (a.mode == kM2Inner ? 2 : 4) * (size_t)base;
-    GQD_HIP(hipMemsetAsync(h->d_sync, 0, sizeof(unsigned) * 2 * (size_t)cnt, stream));
+    // per group [arrivals, abort]; per item [mu ready, gradient done]
+    GQD_HIP(hipMemsetAsync(h->d_sync, 0, sizeof(unsigned) * 2 * (size_t)cnt * (roles + 1), stream));
     GQD_HIP(launch_run2d(h->line_cls, b, stream));
   }
   return GQD_OK;
@@ -152,6 +164,7 @@ K2Args base_args2(const gqd_handle* h) {
   a.sync = h->d_sync;
   a.part = h->d_part;
   a.spin_limit = kSpinLimit;
+  a.roles = 1;
   return a;
 }
 
@@ -279,6 +292,21 @@ gqd_status reorder_by_cost(gqd_handle* h) {
 gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
   GQD_HIP(hipStreamSynchronize(stream));
   GQD_HIP(hipMemcpy(h->h_stats.data(), h->d_stats, sizeof(ItemStats) * h->batch, hipMemcpyDeviceToHost));
+  if (h->dims == 2 && h->stats_roles == 2) {
+    // the second group's solves (mu) of a two-group reverse sweep
+    std::vector<ItemStats> s1(h->batch);
+    GQD_HIP(hipMemcpy(s1.data(), h->d_stats + h->batch, sizeof(ItemStats) * h->batch, hipMemcpyDeviceToHost));
+    for (int b = 0; b < h->batch; ++b) {
+      ItemStats& s = h->h_stats[b];
+      s.h_applies += s1[b].h_applies;
+      s.iterations += s1[b].iterations;
+      s.iterations_sq += s1[b].iterations_sq;
+      s.solves += s1[b].solves;
+      if (s1[b].max_iters > s.max_iters) s.max_iters = s1[b].max_iters;
+      s.failures += s1[b].failures;
+      if (s1[b].nonfinite > s.nonfinite) s.nonfinite = s1[b].nonfinite;
+    }
+  }
   {
     const gqd_status rs = reorder_by_cost(h);
     if (rs != GQD_OK) return rs;
@@ -485,12 +513,14 @@ static gqd_status create2d(gqd_handle** out, const gqd_grid_desc* g) {
   if ((e = hipMalloc(&h->d_tw2, sizeof(double2) * n)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc twiddles"));
   if ((e = hipMemcpy(h->d_tw2, tw.data(), sizeof(double2) * n, hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMemcpy twiddles"));
-  if ((e = hipMalloc(&h->d_sync, sizeof(unsigned) * 2 * (size_t)h->resident_cap)) != hipSuccess)
+  // sync: two words per group and two per item, at most resident_cap of each
+  if ((e = hipMalloc(&h->d_sync, sizeof(unsigned) * 4 * (size_t)h->resident_cap)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMalloc sync"));
   if ((e = hipMalloc(&h->d_part, sizeof(double) * 2 * (size_t)h->resident_cap * kPart2)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMalloc partials"));
-  if ((e = hipMalloc(&h->d_stats, sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc stats"));
-  if ((e = hipMemset(h->d_stats, 0, sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMemset stats"));
+  // statistics of the first group of each item, then of the second (reverse sweep)
+  if ((e = hipMalloc(&h->d_stats, 2 * sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc stats"));
+  if ((e = hipMemset(h->d_stats, 0, 2 * sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMemset stats"));
   if ((e = configure_kernels2d(kMaxRestart)) != hipSuccess) return cleanup(hip_fail(e, "configure kernels"));
   *out = h;
   return GQD_OK;

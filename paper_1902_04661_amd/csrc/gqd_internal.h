@@ -233,8 +233,13 @@ struct K2Args {
   long long nsteps;
   GammaTab gt;
   ItemStats* stats;
-  unsigned* sync;       // per item: [0] arrivals, [1] abort flag (zeroed before launch)
-  double* part;         // per item: [2][G][kPart2]
+  ItemStats* stats1;    // roles = 2: the second group's statistics
+  // groups of G workgroups per item: 1, or 2 for the reverse sweep (phi and mu solved
+  // side by side, each on its own group with its own workspace region)
+  int roles;
+  unsigned* sync;       // per group: [0] arrivals, [1] abort flag; then per item, when
+                        // roles = 2: [0] mu ready, [1] gradient done (zeroed before launch)
+  double* part;         // per group: [2][G][kPart2]
   int spin_limit;       // polls of a grid barrier before it gives up and aborts
 };
 

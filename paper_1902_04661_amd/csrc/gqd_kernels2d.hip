@@ -108,6 +108,45 @@ __device__ bool grid_barrier(GridSync& s, GQD_L double* flag) {
   return uniform_d(*flag) != 0.0;
 }
 
+// One-sided hand-off between the two groups of a reverse sweep: every workgroup of the
+// signalling group adds one to `cnt` after its writes (release); every workgroup of the
+// waiting group polls until `cnt` reaches `target` (acquire).  The wait is bounded like
+// a grid barrier and gives up when either group's abort flag is set.
+__device__ void group_signal(unsigned* cnt) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+__device__ bool group_wait(const unsigned* cnt, unsigned target, unsigned* own_abort, const unsigned* other_abort,
+                           int limit, GQD_L double* flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool ok = true;
+    int polls = 0;
+    for (;;) {
+      const unsigned c = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((int)(c - target) >= 0) break;
+      if (__hip_atomic_load(own_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          __hip_atomic_load(other_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        ok = false;
+        break;
+      }
+      if (++polls > limit) {
+        __hip_atomic_store(own_abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *flag = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  return uniform_d(*flag) != 0.0;
+}
+
 // ---------------------------------------------------------------- reductions
 // Wave-reduce v and record it as slot k of this workgroup's partial.
 __device__ __forceinline__ void put_partial(const Ctx2& c, int k, double v) {
@@ -395,6 +434,10 @@ enum Pc2 {
   k2AdjAfterMu,
   k2AdjAphi,
   k2AdjAmu,
+  k2AdjPhiDone,   // two groups: role 0 has phi, asks for A phi
+  k2AdjGrad,      // two groups: role 0 has A phi; waits for mu, adds the gradient, updates psi
+  k2AdjMuDone,    // two groups: role 1 has mu, asks for A mu
+  k2AdjMuAfter,   // two groups: role 1 has A mu; updates lambda and signals
   k2ApplyDone,
   k2DiagDone,
   k2Inner
@@ -436,8 +479,11 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   using E = G2<NL>;
   constexpr int T = kThreads2;
   const int G = a.G;
-  const int item = blockIdx.x / G;
-  const int g = blockIdx.x - item * G;
+  const int R = a.roles;
+  const int grp = blockIdx.x / G;
+  const int item = grp / R;
+  const int role = grp - item * R;
+  const int g = blockIdx.x - grp * G;
   if (item >= a.batch) return;
   extern __shared__ double2 smem_raw[];
   const int m = a.sc.m;
@@ -447,7 +493,9 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   const Item2 im = a.items[item];
   cplx* psi = (cplx*)a.psi + im.off;
   cplx* lam = (cplx*)a.aux + im.off;
-  cplx* wk = (cplx*)a.work + (size_t)item * a.work_stride;
+  cplx* wk = (cplx*)a.work + (size_t)grp * a.work_stride;
+  // with two groups, role 1 keeps mu in its B slot and A mu in its AR, AC slots
+  cplx* wk1 = (cplx*)a.work + (size_t)(item * R + R - 1) * a.work_stride;
   cplx* X = wk;                   // solve output | phi
   cplx* B = wk + E::VEC;          // rhs          | mu
   cplx* HP = wk + 2 * E::VEC;     // H psi (trapezoid economy)
@@ -462,8 +510,11 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   cplx* AC = wk + 7 * E::VEC;     // A_1 mu
   cplx* basis = wk + kWork2Extra * E::VEC;
   static_assert(kWork2Extra == 10, "workspace slots");
-  GridSync sy{a.sync + 2 * item, a.sync + 2 * item + 1, 0u, G, a.spin_limit};
-  double* part = a.part + (size_t)item * 2 * G * kPart2;
+  GridSync sy{a.sync + 2 * grp, a.sync + 2 * grp + 1, 0u, G, a.spin_limit};
+  unsigned* other_abort = a.sync + 2 * (item * R + (R - 1 - role)) + 1;
+  unsigned* hand = a.sync + 2 * (size_t)a.batch * R + 2 * item;  // [0] mu ready, [1] gradient done
+  unsigned handoffs = 0;  // substeps this group has completed (two-group reverse sweep)
+  double* part = a.part + (size_t)grp * 2 * G * kPart2;
   int par = 0;
   const long long CH = E::VEC / G;
   const long long e0 = (long long)g * CH, e1 = e0 + CH;
@@ -616,7 +667,19 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
       case k2Substep: {
         if (n >= nsteps) goto done;
         alpha = 0.5 * (substep_tau2(cc, a.gt) * dt);
-        if (adj) {
+        if (adj && R == 2) {
+          if (role == 0) {
+            solve_begin(psi, X, -alpha, k2AdjPhiDone);
+          } else {
+            // mu of the previous substep must have been read by the gradient
+            if (!group_wait(hand + 1, handoffs * (unsigned)G, sy.abort_flag, other_abort, a.spin_limit,
+                            c.scal + 15)) {
+              aborted = true;
+              break;
+            }
+            solve_begin(lam, B, -alpha, k2AdjMuDone);
+          }
+        } else if (adj) {
           solve_begin(psi, X, -alpha, k2AdjAfterPhi);
         } else if (midp) {
           solve_begin(psi, X, alpha, k2MidpAfter);
@@ -868,6 +931,53 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         advance();
         break;
       }
+      case k2AdjPhiDone:
+        request(X, false);
+        pc = k2AdjGrad;
+        break;
+      case k2AdjMuDone:
+        rq = LineReq{B, nullptr, nullptr, 0, mk(1.0, 0.0), false, nullptr, false, AR, AC};
+        pending = true;
+        swap_after = false;
+        pc = k2AdjMuAfter;
+        break;
+      case k2AdjMuAfter: {
+        for (long long e = e0 + threadIdx.x; e < e1; e += T) lam[e] = csub(cscale(B[e], 2.0), lam[e]);
+        group_signal(hand);
+        ++handoffs;
+        touched = true;
+        advance();
+        break;
+      }
+      case k2AdjGrad: {
+        // mu, A_2 mu, A_1 mu from the other group's slots
+        if (!group_wait(hand, (handoffs + 1) * (unsigned)G, sy.abort_flag, other_abort, a.spin_limit,
+                        c.scal + 15)) {
+          aborted = true;
+          break;
+        }
+        const cplx* MU = wk1 + E::VEC;
+        const cplx* MR = wk1 + 6 * E::VEC;
+        const cplx* MC = wk1 + 7 * E::VEC;
+        double* gF = a.gF + im.off;
+        const double c1 = -(2.0 * alpha / a.mass1), c0 = -(2.0 * alpha / a.mass0);
+        for (long long p = p0 + threadIdx.x; p < p1; p += T) {
+          const long long i0 = p, i1 = E::NPTS + p;
+          const cplx ph0 = X[i0], ph1 = X[i1], mu0 = MU[i0], mu1 = MU[i1];
+          const double t1 = cconjmul(mu0, OR[i1]).x - cconjmul(mu1, OR[i0]).x +
+                            cconjmul(MR[i0], ph1).x - cconjmul(MR[i1], ph0).x;
+          const double t0 = cconjmul(mu0, OC[i1]).x - cconjmul(mu1, OC[i0]).x +
+                            cconjmul(MC[i0], ph1).x - cconjmul(MC[i1], ph0).x;
+          gF[p] += c0 * t0;
+          gF[E::NPTS + p] += c1 * t1;
+        }
+        for (long long e = e0 + threadIdx.x; e < e1; e += T) psi[e] = csub(cscale(X[e], 2.0), psi[e]);
+        group_signal(hand + 1);
+        ++handoffs;
+        touched = true;
+        advance();
+        break;
+      }
       case k2ApplyDone: {
         cplx* out = (cplx*)a.aux + im.off;
         for (long long e = e0 + threadIdx.x; e < e1; e += T) out[e] = cadd(OR[e], OC[e]);
@@ -924,8 +1034,11 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
     }
   }
 done:
+  // a group that stops early releases the other group of its item from any hand-off wait
+  if (R == 2 && (bad || aborted) && threadIdx.x == 0)
+    __hip_atomic_store(sy.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (g == 0 && threadIdx.x == 0 && a.stats) {
-    ItemStats* st = a.stats + item;
+    ItemStats* st = (role == 0 ? a.stats : a.stats1) + item;
     st->h_applies = napply;
     st->iterations = iters_total;
     st->iterations_sq = iters_sq;
@@ -977,7 +1090,7 @@ hipError_t launch_run2d(int cls, const K2Args& a, hipStream_t stream) {
   K2Args args = a;
   void* params[] = {&args};
   GQD_DISPATCH2(cls, {
-    return hipLaunchCooperativeKernel((const void*)k_run2d<NL>, dim3(a.batch * a.G), dim3(kThreads2), params,
+    return hipLaunchCooperativeKernel((const void*)k_run2d<NL>, dim3(a.batch * a.G * a.roles), dim3(kThreads2), params,
                                       (unsigned)lds_bytes2(NL, a.sc.m), stream);
   });
   return hipSuccess;
