@@ -192,6 +192,14 @@ gqd_status gqd_list_plans(int n, int* radices, int max_plans, int* count);
  * handle from the next call on.  GQD_ERR_UNSUPPORTED if n has no such plan. */
 gqd_status gqd_set_plan(gqd_handle* h, int n, const int* radices);
 
+/* Polls a 2D grid barrier (or a hand-off between the two groups of a 2D reverse sweep)
+ * makes before it gives up (polls >= 1; 0 restores the default of 2^22, about seconds).
+ * When a wait gives up, every workgroup of the item leaves at its next check, the item's
+ * state is left part-way, and a call given a gqd_stats pointer returns GQD_ERR_HIP.  A
+ * small limit makes a stuck launch fail fast (and lets a test reach that path from the
+ * host).  1D handles have no such waits and ignore it.  GQD_ERR_INVALID if polls < 0. */
+gqd_status gqd_set_wait_limit(gqd_handle* h, int polls);
+
 /* Transform autotuner.  Each 1D size class has several Stockham plans (radix orders
  * and threads per item, compiled in); this times every plan that fits in LDS at this
  * restart length on the handle's own items (nsteps composed steps of the given method

@@ -58,6 +58,7 @@ struct gqd_handle {
   double* d_part = nullptr;
   int resident_cap = 0;  // workgroups the partial and sync areas are sized for
   int stats_roles = 1;   // groups per item of the last 2D launch (2: merge their statistics)
+  int spin_limit = 0;    // polls of a 2D grid wait before it gives up (0: the default)
   std::vector<ItemMeta> items;
   long long total_complex = 0;
   std::vector<int> class_lists[kNumClasses];
@@ -163,7 +164,7 @@ K2Args base_args2(const gqd_handle* h) {
   a.mass1 = h->mass2[1];
   a.sync = h->d_sync;
   a.part = h->d_part;
-  a.spin_limit = kSpinLimit;
+  a.spin_limit = h->spin_limit > 0 ? h->spin_limit : kSpinLimit;
   a.roles = 1;
   return a;
 }
@@ -691,6 +692,13 @@ gqd_status gqd_list_plans(int n, int* radices, int max_plans, int* count) {
     ++k;
   }
   *count = k;
+  return GQD_OK;
+}
+
+gqd_status gqd_set_wait_limit(gqd_handle* h, int polls) {
+  if (!h) return fail(GQD_ERR_INVALID, "NULL handle");
+  if (polls < 0) return fail(GQD_ERR_INVALID, "wait limit must be >= 0");
+  h->spin_limit = polls;
   return GQD_OK;
 }
 

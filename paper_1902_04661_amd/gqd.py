@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "gqd_autotune": ([vp, i, i, i, d, ll, vp, ctypes.POINTER(_SolverOpts), vp, vp], i),
         "gqd_list_plans": ([i, vp, i, ctypes.POINTER(i)], i),
         "gqd_set_plan": ([vp, i, vp], i),
+        "gqd_set_wait_limit": ([vp, i], i),
         "gqd_diag": ([vp, vp, vp, vp], i),
         "gqd_inner": ([vp, vp, vp, vp, vp], i),
         "gqd_last_error": ([], ctypes.c_char_p),
@@ -108,7 +109,7 @@ def exported_symbols() -> List[str]:
     return ["gqd_create", "gqd_destroy", "gqd_state_size", "gqd_state_offset",
             "gqd_workspace_size", "gqd_set_workspace", "gqd_set_surfaces", "gqd_apply_H",
             "gqd_implicit_step", "gqd_propagate", "gqd_propagate_items", "gqd_adjoint", "gqd_autotune",
-            "gqd_list_plans", "gqd_set_plan",
+            "gqd_list_plans", "gqd_set_plan", "gqd_set_wait_limit",
             "gqd_diag", "gqd_inner",
             "gqd_last_error"]
 
@@ -314,6 +315,10 @@ class Propagator:
         """Use the transform plan with these radices for items of size n."""
         r = (ctypes.c_int * 4)(*[int(x) for x in radices])
         _check(_lib.gqd_set_plan(self._h, int(n), r))
+
+    def set_wait_limit(self, polls: int) -> None:
+        """Polls a 2D grid wait makes before the item gives up (0: the default)."""
+        _check(_lib.gqd_set_wait_limit(self._h, int(polls)))
 
     def autotune(self, psi: torch.Tensor, method="midp", scheme="suzuki", order: int = 2,
                  dt: float = 1.0, nsteps: int = 1, opts: Optional[SolverOpts] = None, stream=None):

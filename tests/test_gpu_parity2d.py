@@ -151,3 +151,30 @@ def test_adjoint_matches_oracle_2d(gqd):
     print(f"2D adjoint: lambda rel {rl:.2e}, gF_1 rel {rg0:.2e}, gF_2 rel {rg1:.2e}, psi(0) rel {rp:.2e}",
           flush=True)
     assert rl <= 1e-10 and rg0 <= 1e-10 and rg1 <= 1e-10 and rp <= 2e-12
+
+
+def test_wait_limit_gives_up_and_recovers_2d(gqd):
+    # a one-poll limit on the bounded grid waits (forced from the host): the item stops,
+    # every workgroup leaves, the call reports the timeout; the default limit then works
+    it = moving_item(64)
+    prop = gqd.from_items([it])
+    opts = gqd.SolverOpts(tol=1e-14, restart=32)
+    psi = prop.pack([it.psi0])
+    prop.set_wait_limit(1)
+    with pytest.raises(RuntimeError, match="timed out"):
+        prop.propagate(psi, "midp", "suzuki", 4, 10.0, 4, opts)
+    # the two-group reverse sweep gives up the same way
+    lam = prop.pack([it.psi0])
+    gF = torch.zeros(prop.f_size, dtype=torch.float64, device=psi.device)
+    with pytest.raises(RuntimeError, match="timed out"):
+        prop.adjoint(psi, lam, gF, "suzuki", 4, 10.0, 4, opts)
+    with pytest.raises(RuntimeError, match="INVALID"):
+        prop.set_wait_limit(-1)
+    prop.set_wait_limit(0)
+    psi = prop.pack([it.psi0])
+    st = prop.propagate(psi, "midp", "suzuki", 4, 10.0, 2, opts)
+    ref = prop.pack([it.psi0])
+    gqd.from_items([it]).propagate(ref, "midp", "suzuki", 4, 10.0, 2, opts)
+    print(f"after the limit is restored: {st.solves} solves, max |diff| "
+          f"{float((psi - ref).abs().max()):.1e}", flush=True)
+    assert st.nonfinite == 0 and torch.equal(psi, ref)
