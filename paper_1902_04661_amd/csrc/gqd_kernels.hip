@@ -133,8 +133,19 @@ struct Eng {
     return uniform_d(s);
   }
 
+  // Gram-Schmidt stash (two-buffer four-step plans): between transforms the LDS
+  // transform buffers are idle, so the sweep's last turn (the newest one or two basis
+  // vectors) is parked there at each thread's own points (slot q at fft + q 2N) by the
+  // first dot-product sweep and read back by the update and by a second pass.  Each
+  // location is only ever touched by its own thread here, and the four-step transform
+  // touches it only from the same thread or behind its workgroup barriers.
+  static constexpr bool kStash = kFS && kPP;
+  enum { kStashOff = 0, kStashFill = 1, kStashUse = 2 };
+
   // dst[i] = sum conj(V_i) w over the item, i < K (V_i = basis + i*VEC); dst in LDS.
-  // With with_norm, dst[K] = (||w||^2, 0) comes out of the same reduction.
+  // With with_norm, dst[K] = (||w||^2, 0) comes out of the same reduction.  MODE: fill
+  // the stash from the last turn, or read the last turn from it.
+  template <int MODE = kStashOff>
   static __device__ void block_dots(const cplx* __restrict__ basis, const OV& w, int K,
                                     const Ctx& c, GQD_L cplx* dst, bool with_norm = false) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -147,19 +158,45 @@ struct Eng {
 #pragma unroll 1
     for (int i = 0; i < K; i += GSV) {
       const bool two = GSV == 2 && i + 1 < K;
+      const bool last = kStash && MODE != kStashOff && i + GSV >= K;
       const GQD_G cplx* Va = opaque(basis + (size_t)i * VEC);
       const GQD_G cplx* Vb = opaque(basis + (size_t)(two ? i + 1 : i) * VEC);
+      const GQD_L cplx* Sa = c.fft;
+      const GQD_L cplx* Sb = c.fft + (two ? 2 * N : 0);
       double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
 #pragma unroll
       for (int s0 = 0; s0 < 2; s0 += SB) {
         cplx a[SB][R0], b[SB][R0];
+        if (MODE == kStashUse && last) {
 #pragma unroll
-        for (int s = 0; s < SB; ++s)
+          for (int s = 0; s < SB; ++s)
 #pragma unroll
-          for (int r = 0; r < R0; ++r) {
-            a[s][r] = Va[(s0 + s) * N + pt(r)];
-            if constexpr (GSV == 2) b[s][r] = Vb[(s0 + s) * N + pt(r)];
+            for (int r = 0; r < R0; ++r) {
+              a[s][r] = Sa[(s0 + s) * N + pt(r)];
+              if constexpr (GSV == 2) b[s][r] = Sb[(s0 + s) * N + pt(r)];
+            }
+        } else {
+#pragma unroll
+          for (int s = 0; s < SB; ++s)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+              a[s][r] = Va[(s0 + s) * N + pt(r)];
+              if constexpr (GSV == 2) b[s][r] = Vb[(s0 + s) * N + pt(r)];
+            }
+          if (MODE == kStashFill && last) {
+            GQD_L cplx* Wa = c.fft;
+            GQD_L cplx* Wb = c.fft + 2 * N;
+#pragma unroll
+            for (int s = 0; s < SB; ++s)
+#pragma unroll
+              for (int r = 0; r < R0; ++r) {
+                Wa[(s0 + s) * N + pt(r)] = a[s][r];
+                if constexpr (GSV == 2) {
+                  if (two) Wb[(s0 + s) * N + pt(r)] = b[s][r];
+                }
+              }
           }
+        }
 #pragma unroll
         for (int s = 0; s < SB; ++s)
 #pragma unroll
@@ -196,25 +233,41 @@ struct Eng {
   }
 
   // w -= sum_i h[i] V_i, i < K (h in LDS).  All loads of a turn are issued before the
-  // first use, so that a wave keeps them in flight together.
-  static __device__ void block_axpy(const cplx* __restrict__ basis, const GQD_L cplx* h, int K, OV& w) {
+  // first use, so that a wave keeps them in flight together.  USE: the last turn comes
+  // from the stash (filled by the dot-product sweep over the same K).
+  template <bool USE = false>
+  static __device__ void block_axpy(const cplx* __restrict__ basis, const GQD_L cplx* h, int K, OV& w,
+                                    const Ctx& c) {
 #pragma unroll 1
     for (int i = 0; i < K; i += GSV) {
       const bool two = GSV == 2 && i + 1 < K;
+      const bool last = kStash && USE && i + GSV >= K;
       const GQD_G cplx* Va = opaque(basis + (size_t)i * VEC);
       const GQD_G cplx* Vb = opaque(basis + (size_t)(two ? i + 1 : i) * VEC);
+      const GQD_L cplx* Sa = c.fft;
+      const GQD_L cplx* Sb = c.fft + (two ? 2 * N : 0);
       const cplx ha = h[i];
       const cplx hb = two ? h[i + 1] : mk(0.0, 0.0);
 #pragma unroll
       for (int s0 = 0; s0 < 2; s0 += SB) {
         cplx a[SB][R0], b[SB][R0];
+        if (last) {
 #pragma unroll
-        for (int s = 0; s < SB; ++s)
+          for (int s = 0; s < SB; ++s)
 #pragma unroll
-          for (int r = 0; r < R0; ++r) {
-            a[s][r] = Va[(s0 + s) * N + pt(r)];
-            if constexpr (GSV == 2) b[s][r] = Vb[(s0 + s) * N + pt(r)];
-          }
+            for (int r = 0; r < R0; ++r) {
+              a[s][r] = Sa[(s0 + s) * N + pt(r)];
+              if constexpr (GSV == 2) b[s][r] = Sb[(s0 + s) * N + pt(r)];
+            }
+        } else {
+#pragma unroll
+          for (int s = 0; s < SB; ++s)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+              a[s][r] = Va[(s0 + s) * N + pt(r)];
+              if constexpr (GSV == 2) b[s][r] = Vb[(s0 + s) * N + pt(r)];
+            }
+        }
 #pragma unroll
         for (int s = 0; s < SB; ++s)
 #pragma unroll
@@ -1101,7 +1154,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         const double sh = opshift;
         // |w'|^2 = |w|^2 - sum |h_i|^2 when the pass keeps at least half of |w|^2 (a
         // few ulp there); a second pass returns its own |w'|^2 from the same reduction
-        E::block_dots(basis, y, j + 1, c, c.hcol, true);
+        E::template block_dots<E::kStashFill>(basis, y, j + 1, c, c.hcol, true);
         const double w2 = uniform_d(c.hcol[j + 1].x);
         if (j == 0) {  // <v_0|H v_0>, the shift of the following columns and solves
           const double rq = uniform_d(c.hcol[0].x) + sh;
@@ -1110,13 +1163,13 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         double hn2 = w2;
         for (int i = 0; i <= j; ++i) hn2 -= cabs2(c.hcol[i]);
         hn2 = uniform_d(hn2);
-        E::block_axpy(basis, c.hcol, j + 1, y);
+        E::template block_axpy<true>(basis, c.hcol, j + 1, y, c);
         if (hn2 < kReorthRatio * w2) {
-          E::block_dots(basis, y, j + 1, c, c.y, true);
+          E::template block_dots<E::kStashUse>(basis, y, j + 1, c, c.y, true);
           double r2 = uniform_d(c.y[j + 1].x);
           for (int i = 0; i <= j; ++i) r2 -= cabs2(c.y[i]);
           hn2 = uniform_d(r2 > 0.0 ? r2 : 0.0);
-          E::block_axpy(basis, c.y, j + 1, y);
+          E::template block_axpy<true>(basis, c.y, j + 1, y, c);
           for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);
         } else {
           // every wave has read h (above and in block_axpy) before the first wave
