@@ -133,13 +133,14 @@ struct Eng {
     return uniform_d(s);
   }
 
-  // Gram-Schmidt stash (two-buffer four-step plans): between transforms the LDS
-  // transform buffers are idle, so the sweep's last turn (the newest one or two basis
-  // vectors) is parked there at each thread's own points (slot q at fft + q 2N) by the
-  // first dot-product sweep and read back by the update and by a second pass.  Each
-  // location is only ever touched by its own thread here, and the four-step transform
-  // touches it only from the same thread or behind its workgroup barriers.
-  static constexpr bool kStash = kFS && kPP;
+  // Gram-Schmidt stash (four-step plans): between transforms the LDS transform buffers
+  // are idle, so the sweep's last turn (the newest one or two basis vectors) is parked
+  // there at each thread's own points (slot q at fft + q 2N; in-place plans sweep one
+  // vector per turn and use slot 0 only) by the first dot-product sweep and read back
+  // by the update and by a second pass.  Each location is only ever touched by its own
+  // thread here, and the four-step transform touches it only from the same thread or
+  // behind its workgroup barriers.
+  static constexpr bool kStash = kFS && (kPP || GSV == 1);
   enum { kStashOff = 0, kStashFill = 1, kStashUse = 2 };
 
   // dst[i] = sum conj(V_i) w over the item, i < K (V_i = basis + i*VEC); dst in LDS.
