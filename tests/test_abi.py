@@ -45,6 +45,8 @@ def test_invalid_arguments_fail_without_a_gpu():
     h = ctypes.c_void_p()
     assert lib.gqd_create(ctypes.byref(h), None) == -1
     assert b"NULL" in lib.gqd_last_error()
+    assert lib.gqd_set_wait_limit(None, 1) == -1
+    assert b"NULL" in lib.gqd_last_error()
     n = (ctypes.c_int * 1)(300)
     qmin = (ctypes.c_double * 1)(0.0)
     qmax = (ctypes.c_double * 1)(1.0)
