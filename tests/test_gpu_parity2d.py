@@ -153,6 +153,33 @@ def test_adjoint_matches_oracle_2d(gqd):
     assert rl <= 1e-10 and rg0 <= 1e-10 and rg1 <= 1e-10 and rp <= 2e-12
 
 
+def test_adjoint_batch_of_2d_items_matches_oracle(gqd):
+    # three items in one reverse sweep: every item has two groups (phi and mu), its own
+    # pair of workspace regions and hand-off counters, and merged statistics
+    items = [moving_item(64, seed=s, p0=(1.0 + s, -0.5 * s)) for s in (2, 3, 4)]
+    prop = gqd.from_items(items)
+    opts = dict(tol=1e-15, restart=32)
+    psi = prop.pack([it.psi0 for it in items])
+    prop.propagate(psi, "midp", "suzuki", 2, 10.0, 3, gqd.SolverOpts(**opts))
+    lamT = []
+    for it, pT in zip(items, prop.unpack(psi)):
+        lamT.append(O.population_loss(O.model_from_item(it), pT)[1])
+    refs = [O.adjoint(O.model_from_item(it), pT, lT, O.SUZUKI, 2, 10.0, 3, O.SolverOpts(**opts))
+            for it, pT, lT in zip(items, prop.unpack(psi), lamT)]
+    lam = prop.pack(lamT)
+    gF = torch.zeros(prop.f_size, dtype=torch.float64, device=psi.device)
+    st = prop.adjoint(psi, lam, gF, "suzuki", 2, 10.0, 3, gqd.SolverOpts(**opts))
+    assert st.solves == 3 * 2 * 1 * 3 and st.failures == 0 and st.nonfinite == 0
+    g = gF.cpu().numpy().reshape(3, 2, 64 * 64)
+    for b, (it, lo_ref, out_lam, out_psi) in enumerate(zip(items, refs, prop.unpack(lam), prop.unpack(psi))):
+        po, lo, go = lo_ref
+        rl, rp = rel(out_lam, lo), rel(out_psi, it.psi0)
+        rg = max(rel(g[b, 0], go[0].ravel()), rel(g[b, 1], go[1].ravel()))
+        print(f"2D adjoint batch item {b}: lambda rel {rl:.2e}, gF rel {rg:.2e}, psi(0) rel {rp:.2e}",
+              flush=True)
+        assert rl <= 1e-10 and rg <= 1e-10 and rp <= 2e-12
+
+
 def test_wait_limit_gives_up_and_recovers_2d(gqd):
     # a one-poll limit on the bounded grid waits (forced from the host): the item stops,
     # every workgroup leaves, the call reports the timeout; the default limit then works
