@@ -1,0 +1,48 @@
+"""Convergence orders of the composed implicit midpoint on the GPU (Sec. II.D, Eqs. 20-21):
+each scheme runs several step sizes of one packet side by side (per-item steps in one
+launch), and the errors against a fine Suzuki order-8 run fall at the composition's
+order.  Step sizes are chosen per scheme so that the errors stay well above the floor
+that the reference's own solves leave (~3e-11 here: 32 000 solves to 1e-15)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1902_04661_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+T = 480.0
+# scheme, order, step sizes, lowest accepted order of the last (finest) pair
+CASES = [
+    ("suzuki", 2, [60.0, 30.0, 15.0], 1.9),
+    ("triple_jump", 4, [30.0, 15.0, 7.5], 3.8),
+    ("suzuki", 4, [60.0, 30.0, 15.0], 3.8),
+    ("triple_jump", 6, [30.0, 15.0, 7.5], 5.6),
+    ("suzuki", 6, [240.0, 120.0, 60.0], 5.6),
+    ("triple_jump", 8, [30.0, 15.0, 7.5], 7.2),
+    ("suzuki", 8, [240.0, 160.0], 7.2),
+]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_1902_04661_amd import gqd, convergence as C
+    gqd.load_library()
+    item = I.nai_like_item(512, p0=15.0)
+    opts = gqd.SolverOpts(tol=1e-15, restart=48, maxit=4000)
+    ref = C.run_batch(item, "suzuki", 8, [1.875], T, opts, log=lambda *a: None)[1.875]
+    return C, item, opts, ref
+
+
+@pytest.mark.parametrize("scheme,order,dts,lowest", CASES)
+def test_measured_order_matches_the_composition(setup, scheme, order, dts, lowest):
+    C, item, opts, ref = setup
+    runs = C.run_batch(item, scheme, order, dts, T, opts, log=lambda *a: None)
+    errs = [C.grid_norm(item.dq, runs[d] - ref) for d in dts]
+    orders = [math.log(errs[k] / errs[k + 1]) / math.log(dts[k] / dts[k + 1]) for k in range(len(dts) - 1)]
+    print(f"{scheme}-{order}: dt {dts} errors {['%.2e' % e for e in errs]} orders "
+          f"{['%.2f' % p for p in orders]}", flush=True)
+    assert errs[-1] > 5e-11, "the finest error must stay above the reference's floor"
+    assert lowest <= orders[-1] <= order + 0.5
+    assert all(np.diff(errs) < 0)  # smaller steps, smaller errors
