@@ -907,7 +907,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
   bool sod_started = false;
 
   // operator request: H - opshift applied to opsrc (opshift = 0 outside Arnoldi)
-  bool pending = false, opH = false;
+  bool pending = false, opH = false, op_in_y = false;
   int half = 0;
   const cplx* opsrc = nullptr;
   double opshift = 0.0;
@@ -924,11 +924,13 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
   int pc = kSubstep;
   OV y, keep;
 
-  auto request = [&](const cplx* src, bool h, double shift = 0.0) {
+  // in_y: the operand was just stored from y, which still holds it at owned points
+  auto request = [&](const cplx* src, bool h, double shift = 0.0, bool in_y = false) {
     pending = true;
     opsrc = src;
     opH = h;
     opshift = shift;
+    op_in_y = in_y;
     half = 0;
   };
   // start a solve of (1 + i al H) x = b: ||b||, then ask for H b
@@ -976,7 +978,11 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
       // (two-buffer mode) or read from opsrc / parked in the CHI slot (larger N)
       OV t;
       if (half == 0) {
-        E::load(t, opsrc);
+        if (op_in_y) {
+          t = y;
+        } else {
+          E::load(t, opsrc);
+        }
         if constexpr (E::kPP) keep = t;
       } else {
         t = y;
@@ -1102,7 +1108,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
           for (int r = 0; r < R0; ++r) y.v[s][r] = csub(t.v[s][r], cmul_is(y.v[s][r], al));
         E::store(y, xg);  // x0 = (1 - i al H) b
-        request(xg, true);
+        request(xg, true, 0.0, true);
         pc = kSolveResid;
         break;
       }
@@ -1139,7 +1145,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         if (threadIdx.x == 0) c.g[0] = mk(beta, 0.0);
         // (the next block reduction's barrier orders this write before any read)
         j = 0;
-        request(basis, true, kind_mu ? sig1 : sig0);
+        request(basis, true, kind_mu ? sig1 : sig0, true);
         pc = kSolveArnoldi;
         break;
       }
@@ -1202,7 +1208,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
             for (int r = 0; r < R0; ++r) y.v[s][r] = cmul_is(y.v[s][r], sc);
           ++j;
           E::store(y, basis + (size_t)j * E::VEC);
-          request(basis + (size_t)j * E::VEC, true, kind_mu ? sig1 : sig0);
+          request(basis + (size_t)j * E::VEC, true, kind_mu ? sig1 : sig0, true);
           break;
         }
         // cycle ends: x += V y over the k = j + 1 basis vectors
