@@ -46,9 +46,9 @@ TOL = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "2b0eb26597e5bb1d8f6eeaa95020005c4e5943b82a9c55dce87beafa3870c42f",
-    "fetch_kib": 109745745.5625, "fetch_scale": 2.0,
-    "write_kib": 56882094.75, "write_scale": 1.0,
+    "sources_sha256": "dbe443f9b0b7ccc041c3ad7edd44d1d97bfa0fd5e8fa2df9fd59849c42a27129",
+    "fetch_kib": 90830310.9375, "fetch_scale": 2.0,
+    "write_kib": 56879532.125, "write_scale": 1.0,
     "alg_bytes_same_launch": 330511155200.0,
     "summary": "profiles/k_run_2048_sz8_x1024.md",
 }
