@@ -908,6 +908,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
 
   // operator request: H - opshift applied to opsrc (opshift = 0 outside Arnoldi)
   bool pending = false, opH = false, op_in_y = false;
+  bool psi_in_y = false;  // y holds psi at owned points (set by the midpoint update)
   int half = 0;
   const cplx* opsrc = nullptr;
   double opshift = 0.0;
@@ -933,8 +934,9 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
     op_in_y = in_y;
     half = 0;
   };
-  // start a solve of (1 + i al H) x = b: ||b||, then ask for H b
-  auto solve_begin = [&](const cplx* b, cplx* x, double alv, int ret) {
+  // start a solve of (1 + i al H) x = b: ||b||, then ask for H b.  b_in_y: y holds b
+  // (the midpoint's new state, just stored), so neither needs to read it back.
+  auto solve_begin = [&](const cplx* b, cplx* x, double alv, int ret, bool b_in_y = false) {
     bg = b;
     xg = x;
     al = alv;
@@ -942,11 +944,15 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
     kind_mu = ret == kAdjAfterMu;
     iters = 0;
     OV t;
-    E::load(t, b);
+    if (b_in_y) {
+      t = y;
+    } else {
+      E::load(t, b);
+    }
     const double bnorm = sqrt(E::block_sum1(E::norm2(t), c));
     if (!isfinite(bnorm)) bad = true;
     tolb = a.sc.tol * bnorm;
-    request(b, true);
+    request(b, true, 0.0, b_in_y);
     pc = kSolveGuess;
   };
   auto solve_end = [&](bool conv) {
@@ -1027,7 +1033,8 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         if (adj) {
           solve_begin(psi, S0, -alpha, kAdjAfterPhi);
         } else if (midp) {
-          solve_begin(psi, S0, alpha, kMidpAfter);
+          solve_begin(psi, S0, alpha, kMidpAfter, psi_in_y);
+          psi_in_y = false;
         } else if (literal || !have_hpsi) {
           request(psi, true);
           pc = kTrapHpsi;
@@ -1078,14 +1085,15 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           pc = kMidpExplicit;
           break;
         }
-        OV p, q;  // psi' = 2x - psi
+        OV q;  // psi' = 2x - psi, left in y for the next substep's solve
         E::load(q, S0);
-        E::load(p, psi);
+        E::load(y, psi);
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-          for (int r = 0; r < R0; ++r) p.v[s][r] = csub(cscale(q.v[s][r], 2.0), p.v[s][r]);
-        E::store(p, psi);
+          for (int r = 0; r < R0; ++r) y.v[s][r] = csub(cscale(q.v[s][r], 2.0), y.v[s][r]);
+        E::store(y, psi);
+        psi_in_y = true;
         advance();
         break;
       }
