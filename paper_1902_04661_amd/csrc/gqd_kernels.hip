@@ -1225,24 +1225,40 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         {
           OV x;
           E::load(x, xg);
+          // the last turn's vectors are still in the Gram-Schmidt stash (the last
+          // Arnoldi step swept the same k); not on in-place plans, whose registers
+          // are exhausted here
 #pragma unroll 1
           for (int i = 0; i < k; i += E::GSV) {
             const bool two = E::GSV == 2 && i + 1 < k;
+            const bool last = E::kStash && E::kPP && i + E::GSV >= k;
             const GQD_G cplx* Va = opaque(basis + (size_t)i * E::VEC);
             const GQD_G cplx* Vb = opaque(basis + (size_t)(two ? i + 1 : i) * E::VEC);
+            const GQD_L cplx* Sa = c.fft;
+            const GQD_L cplx* Sb = c.fft + (two ? 2 * N : 0);
             const cplx ya = c.y[i];
             const cplx yb = two ? c.y[i + 1] : mk(0.0, 0.0);
             constexpr int SB = E::SB;
 #pragma unroll
             for (int s0 = 0; s0 < 2; s0 += SB) {
               cplx va[SB][R0], vb[SB][R0];
+              if (last) {
 #pragma unroll
-              for (int s = 0; s < SB; ++s)
+                for (int s = 0; s < SB; ++s)
 #pragma unroll
-                for (int r = 0; r < R0; ++r) {
-                  va[s][r] = Va[(s0 + s) * N + E::pt(r)];
-                  if constexpr (E::GSV == 2) vb[s][r] = Vb[(s0 + s) * N + E::pt(r)];
-                }
+                  for (int r = 0; r < R0; ++r) {
+                    va[s][r] = Sa[(s0 + s) * N + E::pt(r)];
+                    if constexpr (E::GSV == 2) vb[s][r] = Sb[(s0 + s) * N + E::pt(r)];
+                  }
+              } else {
+#pragma unroll
+                for (int s = 0; s < SB; ++s)
+#pragma unroll
+                  for (int r = 0; r < R0; ++r) {
+                    va[s][r] = Va[(s0 + s) * N + E::pt(r)];
+                    if constexpr (E::GSV == 2) vb[s][r] = Vb[(s0 + s) * N + E::pt(r)];
+                  }
+              }
 #pragma unroll
               for (int s = 0; s < SB; ++s)
 #pragma unroll
