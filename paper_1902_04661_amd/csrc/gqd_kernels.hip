@@ -563,16 +563,22 @@ struct Eng {
   static __device__ void kinetic_fs(const OV& x, OV& u, const Ctx& c, double ktau) {
     GQD_L cplx* b0 = c.fft;                          // forward exchange
     GQD_L cplx* b1 = kPP ? c.fft + 2 * N : c.fft;    // slab work and the way back
-    // inner radix-R0 DFT on owned points, outer twiddle w_N^(t k1), exchange
+    // inner radix-R0 DFT on owned points, outer twiddle w_N^(t k1) (the same for both
+    // surfaces, loaded once), exchange
+    cplx wo[R0 - 1];
+    {
+      const GQD_G cplx* tk = opaque(c.tw) + pass_table_offset(PLAN, 0) + lane_tid() * (R0 - 1);
+#pragma unroll
+      for (int k1 = 1; k1 < R0; ++k1) wo[k1 - 1] = tk[k1 - 1];
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       cplx y[R0];
 #pragma unroll
       for (int r = 0; r < R0; ++r) y[r] = x.v[s][r];
       DFT<R0, -1>::run(y);
-      const GQD_G cplx* tk = opaque(c.tw) + pass_table_offset(PLAN, 0) + lane_tid() * (R0 - 1);
 #pragma unroll
-      for (int k1 = 1; k1 < R0; ++k1) y[k1] = cmul(y[k1], tk[k1 - 1]);
+      for (int k1 = 1; k1 < R0; ++k1) y[k1] = cmul(y[k1], wo[k1 - 1]);
       const int t = lane_tid();
 #pragma unroll
       for (int k1 = 0; k1 < R0; ++k1) b0[(s * R0 + k1) * M + t] = y[k1];
