@@ -46,9 +46,9 @@ TOL = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "9d85abc394f96754fbc2252ab701ab87f121ad73109d57da5a3e5d18678410f4",
-    "fetch_kib": 81645531.75, "fetch_scale": 2.0,
-    "write_kib": 56881652.5, "write_scale": 1.0,
+    "sources_sha256": "c3bb69a4e01987dba989ee77a37fc2f006af6a4148de4c16f0f82ebefca87f98",
+    "fetch_kib": 81843250.5625, "fetch_scale": 2.0,
+    "write_kib": 56882971.75, "write_scale": 1.0,
     "alg_bytes_same_launch": 330511155200.0,
     "summary": "profiles/k_run_2048_sz8_x1024.md",
 }
