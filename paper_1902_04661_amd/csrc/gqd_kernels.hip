@@ -894,7 +894,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
   cplx* S0 = work + (size_t)(m + 1) * E::VEC;  // X (solve output)  | PHI
   cplx* S1 = S0 + E::VEC;                       // B (rhs, H x)      | MU
   cplx* S2 = S1 + E::VEC;                       // HPSI              | A phi
-  cplx* S3 = S2 + E::VEC;                       //                   | A mu
+  cplx* S3 = S2 + E::VEC;                       //                   | (spare: A mu stays in registers)
   cplx* CHI = S3 + E::VEC;                      // inner A x of an H application
   const bool adj = a.mode == 1;
   const bool midp = a.method == kMidp;
@@ -1298,7 +1298,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         pc = kAdjAmu;
         break;
       case kAdjAmu: {
-        E::store(y, S3);
+        // y = A mu at owned points (surface s of point r in y.v[s][r])
         double* gF = a.gF + im.foff;
         const double coef = -(2.0 * alpha / a.mass);
         double tg[R0], g[R0];
@@ -1306,7 +1306,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         for (int r = 0; r < R0; ++r) {
           const int i0 = E::pt(r), i1 = N + E::pt(r);
           tg[r] = cconjmul(S1[i0], S2[i1]).x - cconjmul(S1[i1], S2[i0]).x +
-                  cconjmul(S3[i0], S0[i1]).x - cconjmul(S3[i1], S0[i0]).x;
+                  cconjmul(y.v[0][r], S0[i1]).x - cconjmul(y.v[1][r], S0[i0]).x;
         }
 #pragma unroll
         for (int r = 0; r < R0; ++r) g[r] = gF[E::pt(r)];
