@@ -1030,7 +1030,8 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           if (a.method == kEulerImpl) {
             solve_begin(psi, S0, alpha, kImplAfter);
           } else {
-            request(psi, true);
+            request(psi, true, 0.0, psi_in_y);
+            psi_in_y = false;
             pc = a.method == kEulerExpl ? kExplAfter : (sod_started ? kSodStep : kSodStart);
           }
           break;
@@ -1339,6 +1340,8 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
           for (int r = 0; r < R0; ++r) p.v[s][r] = csub(p.v[s][r], cmul_is(y.v[s][r], alpha));
         E::store(p, psi);
+        y = p;  // the next step's operator input
+        psi_in_y = true;
         advance();
         break;
       }
@@ -1386,6 +1389,8 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           for (int r = 0; r < R0; ++r) q.v[s][r] = csub(q.v[s][r], cmul_is(y.v[s][r], 2.0 * alpha));
         E::store(p, S1);
         E::store(q, psi);
+        y = q;  // the next step's operator input
+        psi_in_y = true;
         advance();
         break;
       }
