@@ -46,9 +46,9 @@ TOL = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "ca3427510b6886b8c51e2f7e16b7109a7dc4f595262c89e090cf75f081edb8ca",
-    "fetch_kib": 81287146.1875, "fetch_scale": 2.0,
-    "write_kib": 56882044.25, "write_scale": 1.0,
+    "sources_sha256": "4b6731f3a4c6e76581b18648d82b3e2c2f496015a576d22917c0f8ac8f4a595f",
+    "fetch_kib": 81256669.5, "fetch_scale": 2.0,
+    "write_kib": 56882301.625, "write_scale": 1.0,
     "alg_bytes_same_launch": 330511155200.0,
     "summary": "profiles/k_run_2048_sz8_x1024.md",
 }
