@@ -92,10 +92,17 @@ typedef enum {
                              TRAP and MIDP (Sec. II.D).  1D only. */
 } gqd_method;
 
-/* Recursive symmetric composition (Sec. II.D). */
+/* Symmetric composition of the second-order methods (Sec. II.D). */
 typedef enum {
-  GQD_TRIPLE_JUMP = 0, /* M = 3, Eq. (20) */
-  GQD_SUZUKI = 1       /* M = 5, Eq. (21) */
+  GQD_TRIPLE_JUMP = 0, /* recursive, M = 3 per level, Eq. (20) */
+  GQD_SUZUKI = 1,      /* recursive, M = 5 per level, Eq. (21) */
+  GQD_OPTIMAL = 2      /* non-recursive: one symmetric composition of the second-order
+                          method with the fewest substeps for its order and the
+                          smallest largest |substep| (orders 4, 6, 8: M = 5, 9, 17), or
+                          the smallest sum of |substeps| (order 10: M = 35), the
+                          optimisation criteria Sec. II.D names for these schemes; the
+                          fractions were derived here from the order conditions
+                          (gqd_composition returns them) */
 } gqd_scheme;
 
 typedef struct {
@@ -116,6 +123,12 @@ typedef struct {
   int literal; /* 1: perform every explicit half-step (3 + I H-applications per substep,
                   Table I); 0: use the Cayley identities (midpoint psi' = 2x - psi,
                   trapezoid reuses H psi' = (b - psi')/(i a)), 2 + I per substep */
+  int verify;  /* 1: when the residual estimate meets the tolerance, form x, compute the
+                  TRUE residual b - (1 + i a H) x (one more H application) and end the
+                  solve only if it meets the tolerance too, else restart GMRES from x;
+                  gqd_stats.max_true_resid then covers every solve.  0: stop on the
+                  estimate (Sec. II.C solves to machine accuracy; the estimate is the
+                  usual GMRES stop test) */
 } gqd_solver_opts;
 
 typedef struct {
@@ -130,6 +143,10 @@ typedef struct {
   double alg_bytes;     /* algorithmic memory traffic of the call: 32 (I^2 + 4I + 8) bytes
                            per grid point per solve of I iterations (two complex128
                            surfaces, one Gram-Schmidt pass, fused H application) */
+  double max_true_resid; /* largest |b - (1 + i a H) x| / |b| over the solves that ended
+                            on a true residual: every solve with verify = 1; without it
+                            only those that ended at their initial residual or after a
+                            restart (0 if none did) */
 } gqd_stats;
 
 typedef struct gqd_handle gqd_handle;
@@ -191,6 +208,22 @@ gqd_status gqd_list_plans(int n, int* radices, int max_plans, int* count);
 /* Use the plan with these radices (host int[4]) for every item of size n on this
  * handle from the next call on.  GQD_ERR_UNSUPPORTED if n has no such plan. */
 gqd_status gqd_set_plan(gqd_handle* h, int n, const int* radices);
+
+/* Per-solve record (optional): from the next call on, the Arnoldi iteration count of
+ * the s-th GMRES solve of item b within a call is written to log[b * per_item + s]
+ * for s < per_item (later solves are not recorded).  log is a DEVICE int array of
+ * batch * per_item entries owned by the caller; it must stay valid while set.  Solves
+ * are numbered in the order the item performs them (substeps in order of application;
+ * a reverse sweep solves phi, then mu, per substep: phi at even and mu at odd s).
+ * per_item = 0 (log may be NULL) switches the record off.  GQD_ERR_INVALID if
+ * per_item < 0, or per_item > 0 with a NULL log. */
+gqd_status gqd_set_solve_log(gqd_handle* h, int* log, long long per_item);
+
+/* The substep fractions tau_c (step c has length tau_c dt) of one composed step, in
+ * the order they are applied: tau (host) receives *count values when it is not NULL and
+ * max_tau >= *count.  Needs no handle or device.  GQD_ERR_UNSUPPORTED for an order
+ * without such a scheme. */
+gqd_status gqd_composition(gqd_scheme s, int order, double* tau, int max_tau, int* count);
 
 /* Polls a 2D grid barrier (or a hand-off between the two groups of a 2D reverse sweep)
  * makes before it gives up (polls >= 1; 0 restores the default of 2^22, about seconds).

@@ -212,12 +212,14 @@ class SolverOpts:
     restart: int = 64      # Krylov dimension m before a restart
     maxit: int = 1000      # total Arnoldi iterations allowed per solve
     literal: bool = False  # True: perform every explicit half-step (3 + I applies)
+    verify: bool = False   # True: confirm convergence on the true residual (restart if not met)
 
 
 @dataclass
 class SolveInfo:
     iterations: int
     converged: bool
+    true_resid: float = float("nan")  # |b - A x| / |b| when the solve ended on it
 
 
 @dataclass
@@ -227,6 +229,7 @@ class Stats:
     iterations: int = 0
     max_iters: int = 0
     failures: int = 0
+    max_true_resid: float = 0.0
     per_solve: List[int] = field(default_factory=list)
 
     def record(self, info: SolveInfo):
@@ -234,6 +237,8 @@ class Stats:
         self.iterations += info.iterations
         self.max_iters = max(self.max_iters, info.iterations)
         self.per_solve.append(info.iterations)
+        if info.converged and not math.isnan(info.true_resid):
+            self.max_true_resid = max(self.max_true_resid, info.true_resid)
         if not info.converged:
             self.failures += 1
 
@@ -252,11 +257,13 @@ def givens(a: complex, b: float) -> Tuple[float, complex, complex]:
 
 
 def gmres(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, x0: np.ndarray,
-          tol: float, m: int, maxit: int) -> Tuple[np.ndarray, SolveInfo]:
+          tol: float, m: int, maxit: int, verify: bool = False) -> Tuple[np.ndarray, SolveInfo]:
     """Restarted GMRES(m) (Saad & Schultz) for A x = b from x0 (Sec. II.C).
 
     Arnoldi with modified Gram-Schmidt, least squares by Givens rotations; the stop
-    rule is the residual estimate |g_{j+1}| <= tol * ||b||."""
+    rule is the residual estimate |g_{j+1}| <= tol * ||b||.  With verify, a solve that
+    meets it forms x and ends only if the true residual |b - A x| meets the tolerance
+    as well; otherwise GMRES restarts from that x."""
     bnorm = float(np.linalg.norm(b))
     x = x0.copy()
     iters = 0
@@ -264,7 +271,7 @@ def gmres(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, x0: np.ndar
         r = b - matvec(x)
         beta = float(np.linalg.norm(r))
         if beta <= tol * bnorm:
-            return x, SolveInfo(iters, True)
+            return x, SolveInfo(iters, True, beta / bnorm if bnorm > 0.0 else 0.0)
         if iters >= maxit:
             return x, SolveInfo(iters, False)
         basis = np.zeros((m + 1, b.size), dtype=np.complex128)
@@ -303,7 +310,7 @@ def gmres(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, x0: np.ndar
         for i in range(k - 1, -1, -1):                  # back substitution R y = g
             y[i] = (g[i] - np.dot(R[i, i + 1:k], y[i + 1:k])) / R[i, i]
         x = x + basis[:k].T @ y
-        if converged:
+        if converged and not verify:
             return x, SolveInfo(iters, True)
 
 
@@ -330,7 +337,7 @@ def implicit_euler(model: Model, psi: np.ndarray, eps: float, opts: SolverOpts,
         return v + 1j * eps * apply_H(model, v.reshape(shape), counter).ravel()
 
     x0 = explicit_euler(model, psi, eps, counter)
-    x, info = gmres(matvec, psi.ravel(), x0.ravel(), opts.tol, opts.restart, opts.maxit)
+    x, info = gmres(matvec, psi.ravel(), x0.ravel(), opts.tol, opts.restart, opts.maxit, opts.verify)
     stats.record(info)
     stats.h_applies += counter.h_applies
     return x.reshape(shape)

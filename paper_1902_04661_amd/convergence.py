@@ -17,7 +17,7 @@ import json
 import math
 import sys
 import time
-from typing import Dict, List
+from typing import Dict, List, Sequence
 
 import numpy as np
 import torch
@@ -44,12 +44,12 @@ def phase_error(psi: np.ndarray, ref: np.ndarray) -> float:
     return abs(math.remainder(d, 2.0 * math.pi))
 
 
-def run_batch(item, scheme: str, order: int, dts: List[float], T: float, opts: gqd.SolverOpts,
-              chunk: int = 64, log=print) -> Dict[float, np.ndarray]:
-    """Propagate copies of `item` to time T, copy b with step dts[b]; return the states."""
-    items = [item] * len(dts)
-    prop = gqd.from_items(items)
-    psi = prop.pack([item.psi0] * len(dts))
+def run_items(items, scheme: str, order: int, dts: Sequence[float], T: float, opts: gqd.SolverOpts,
+              chunk: int = 64, log=print) -> List[np.ndarray]:
+    """Propagate items[b] with step dts[b] to time T (implicit midpoint, one batched
+    launch per chunk of steps, each item with its own step); return the final states."""
+    prop = gqd.from_items(list(items))
+    psi = prop.pack([it.psi0 for it in items])
     nsteps = np.array([int(round(T / dt)) for dt in dts], dtype=np.int64)
     for dt, ns in zip(dts, nsteps):
         if abs(ns * dt - T) > 1e-9 * T:
@@ -58,11 +58,30 @@ def run_batch(item, scheme: str, order: int, dts: List[float], T: float, opts: g
     t0 = time.time()
     while np.any(done < nsteps):
         step = np.minimum(nsteps - done, chunk)
-        st = prop.propagate_items(psi, "midp", scheme, order, dt=np.asarray(dts), nsteps=step, opts=opts)
+        st = prop.propagate_items(psi, "midp", scheme, order, dt=np.asarray(dts, dtype=np.float64),
+                                  nsteps=step, opts=opts)
         done += step
         log(f"  {scheme}-{order}: {int(done.min())}..{int(done.max())} of {int(nsteps.max())} steps, "
             f"{time.time() - t0:.1f} s, mean GMRES iterations {st.iterations / max(st.solves, 1):.2f}")
-    return {dt: s for dt, s in zip(dts, prop.unpack(psi))}
+    out = prop.unpack(psi)
+    prop.close()
+    return out
+
+
+def run_batch(item, scheme: str, order: int, dts: List[float], T: float, opts: gqd.SolverOpts,
+              chunk: int = 64, log=print) -> Dict[float, np.ndarray]:
+    """Propagate copies of `item` to time T, copy b with step dts[b]; return the states."""
+    states = run_items([item] * len(dts), scheme, order, dts, T, opts, chunk, log)
+    return {dt: s for dt, s in zip(dts, states)}
+
+
+def step_errors(items, scheme: str, order: int, dt: float, T: float, opts: gqd.SolverOpts,
+                chunk: int = 64, log=print) -> List[float]:
+    """Convergence error of each item at time T for one step dt: the scheme's run against
+    the order-8 Suzuki run at dt / 8 (grid L2 norm)."""
+    runs = run_items(items, scheme, order, [dt] * len(items), T, opts, chunk, log)
+    refs = run_items(items, "suzuki", 8, [dt / 8.0] * len(items), T, opts, chunk, log)
+    return [grid_norm(it.dq, a - r) for it, a, r in zip(items, runs, refs)]
 
 
 def sweep(item, T: float = 4000.0, dt0: float = 40.0, kmax: int = 3, order: int = 8,
@@ -86,6 +105,56 @@ def sweep(item, T: float = 4000.0, dt0: float = 40.0, kmax: int = 3, order: int 
     return result
 
 
+def packet_set(n: int = 2048, draws: int = 6, seed: int = 0, pool: int = 1024) -> List:
+    """Packets for the step-size study at grid size n: the model's resting packet
+    (q0 = 5, p0 = 0), a moving one (q0 = 5.05, p0 = 2.5; the second state of Sec. III's
+    symplectic-form test), and the `draws` fastest (largest |p0|) of `pool` seeded
+    ragged-batch draws on that grid (q0 ~ U[4.5, 6], p0 ~ U[-5, 5], coupling amplitude
+    ~ U[0.1, 0.8]): the fastest packets carry the largest kinetic energies and with them
+    the largest time-discretisation errors."""
+    d = inputs.ragged_batch_draws(pool, seed)
+    order = np.argsort(-np.abs(d["p0"]), kind="stable")[:draws]
+    items = [inputs.nai_like_item(n), inputs.nai_like_item(n, q0=5.05, p0=2.5)]
+    for b in order:
+        items.append(inputs.nai_like_item(n, q0=float(d["q0"][b]), p0=float(d["p0"][b]), amp=float(d["amp"][b])))
+    return items
+
+
+def multi_sweep(items, T: float = 4000.0, dt0: float = 40.0, kmax: int = 3, tj_shift: int = 1,
+                tol: float = 1e-15, restart: int = 48, chunk: int = 200, log=print) -> dict:
+    """Order-8 Suzuki at dt_k = dt0 2^-k (k <= kmax) and order-8 triple jump at dt_(k+tj_shift),
+    each against the Suzuki-8 run at a step eight times smaller, for every packet; and the
+    floor of the references: the two finest Suzuki-8 runs against each other."""
+    opts = gqd.SolverOpts(tol=tol, restart=restart, maxit=4000)
+    ks = kmax + tj_shift + 3  # the finest level: the last triple-jump run's reference
+    dts = [dt0 * 2.0 ** (-k) for k in range(ks + 1)]
+    P = len(items)
+    sz = run_items([it for it in items for _ in dts], "suzuki", 8, [dt for _ in items for dt in dts], T,
+                   opts, chunk, log)
+    sz = [sz[p * len(dts):(p + 1) * len(dts)] for p in range(P)]
+    tj_k = list(range(tj_shift, kmax + tj_shift + 1))
+    tj = run_items([it for it in items for _ in tj_k], "triple_jump", 8,
+                   [dts[k] for _ in items for k in tj_k], T, opts, chunk, log)
+    tj = [tj[p * len(tj_k):(p + 1) * len(tj_k)] for p in range(P)]
+    out = {"T": T, "tol": tol, "n": items[0].n, "dt_suzuki": dts[:kmax + 1], "dt_triple_jump": [dts[k] for k in tj_k],
+           "packets": []}
+    for p, it in enumerate(items):
+        e_sz = [grid_norm(it.dq, sz[p][k] - sz[p][k + 3]) for k in range(kmax + 1)]
+        e_tj = [grid_norm(it.dq, tj[p][i] - sz[p][k + 3]) for i, k in enumerate(tj_k)]
+        floor = grid_norm(it.dq, sz[p][ks - 1] - sz[p][ks])
+        out["packets"].append({"q0": it.params["q0"], "p0": it.params["p0"], "amp": it.params["amp"],
+                               "suzuki8": e_sz, "triple_jump8": e_tj, "reference_floor": floor,
+                               "reference_floor_dt": [dts[ks - 1], dts[ks]]})
+        log(f"packet q0={it.params['q0']:.3f} p0={it.params['p0']:+.3f}: SZ-8 {['%.1e' % e for e in e_sz]} "
+            f"TJ-8 {['%.1e' % e for e in e_tj]} floor {floor:.1e}")
+    for key, dtl in (("suzuki8", out["dt_suzuki"]), ("triple_jump8", out["dt_triple_jump"])):
+        worst = [max(pk[key][k] for pk in out["packets"]) for k in range(len(dtl))]
+        ok = [dtl[k] for k in range(len(dtl)) if worst[k] <= 1e-10]
+        out.setdefault("worst", {})[key] = worst
+        out.setdefault("dt_star", {})[key] = max(ok) if ok else None
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--n", type=int, default=2048)
@@ -95,11 +164,18 @@ def main(argv=None):
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-14)
     ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--draws", type=int, default=-1,
+                    help="packet set: the resting and moving packets plus this many fastest draws "
+                         "(order 8, Suzuki and triple jump)")
     ap.add_argument("--json", type=str, default="")
     args = ap.parse_args(argv)
-    item = inputs.nai_like_item(args.n)
-    res = sweep(item, args.T, args.dt0, args.kmax, args.order, tol=args.tol, chunk=args.chunk,
-                log=lambda m: print(m, flush=True))
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    if args.draws >= 0:
+        res = multi_sweep(packet_set(args.n, args.draws), args.T, args.dt0, args.kmax, tol=args.tol,
+                          chunk=args.chunk, log=log)
+    else:
+        item = inputs.nai_like_item(args.n)
+        res = sweep(item, args.T, args.dt0, args.kmax, args.order, tol=args.tol, chunk=args.chunk, log=log)
     print(json.dumps(res), flush=True)
     if args.json:
         with open(args.json, "w") as f:

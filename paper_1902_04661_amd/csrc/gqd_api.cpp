@@ -11,6 +11,7 @@
 
 #include "gqd.h"
 #include "gqd_internal.h"
+#include "gqd_compositions.h"
 
 using namespace gqd;
 
@@ -73,6 +74,8 @@ struct gqd_handle {
   const double* F = nullptr;
   void* work = nullptr;
   size_t work_bytes = 0;
+  int* solve_log = nullptr;  // optional per-solve iteration counts, log_cap per item
+  long long log_cap = 0;
   hipStream_t side[kNumClasses] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kNumClasses] = {};
@@ -247,8 +250,21 @@ KArgs base_args(const gqd_handle* h) {
 gqd_status make_gammas(gqd_scheme s, int order, GammaTab* gt) {
   if (order < 2 || order % 2 || order > 2 * (kMaxLevels + 1))
     return fail(GQD_ERR_INVALID, "order must be even, 2..10");
-  if (s != GQD_TRIPLE_JUMP && s != GQD_SUZUKI) return fail(GQD_ERR_INVALID, "unknown composition scheme");
+  if (s != GQD_TRIPLE_JUMP && s != GQD_SUZUKI && s != GQD_OPTIMAL)
+    return fail(GQD_ERR_INVALID, "unknown composition scheme");
   std::memset(gt, 0, sizeof(*gt));
+  if (s == GQD_OPTIMAL) {
+    // one level of fractions over the second-order method (gqd_compositions.h)
+    for (int k = 0; k < kNumFlat; ++k)
+      if (kFlatComps[k].order == order) {
+        gt->flat = 1 + kFlatComps[k].offset;
+        gt->count = kFlatComps[k].count;
+        gt->arity = kFlatComps[k].count;
+        gt->levels = 1;
+        return GQD_OK;
+      }
+    return fail(GQD_ERR_UNSUPPORTED, "no non-recursive composition of order " + std::to_string(order));
+  }
   gt->arity = (s == GQD_TRIPLE_JUMP) ? 3 : 5;
   gt->levels = order / 2 - 1;
   gt->count = 1;
@@ -306,6 +322,7 @@ gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
       if (s1[b].max_iters > s.max_iters) s.max_iters = s1[b].max_iters;
       s.failures += s1[b].failures;
       if (s1[b].nonfinite > s.nonfinite) s.nonfinite = s1[b].nonfinite;
+      if (s1[b].max_resid > s.max_resid) s.max_resid = s1[b].max_resid;
     }
   }
   {
@@ -323,6 +340,7 @@ gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
     if (s.max_iters > st->max_iters) st->max_iters = s.max_iters;
     st->failures += s.failures;
     st->nonfinite += s.nonfinite;
+    if (s.max_resid > st->max_true_resid) st->max_true_resid = s.max_resid;
     // 32 (I^2 + 4 I + 8) bytes per grid point per solve (S = 2 complex128 vectors)
     const double pts = h->dims == 2 ? (double)h->n2 * h->n2 : (double)h->items[b].n;
     st->alg_bytes += 32.0 * pts *
@@ -635,7 +653,7 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
     a.mode = kM2Propagate;
     a.psi = (double2*)psi;
     a.work = (double2*)h->work;
-    a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+    a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
     a.method = (m == GQD_TRAP) ? kTrap : kMidp;
     a.dt = dt;
     a.nsteps = nsteps;
@@ -649,7 +667,7 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   if (s != GQD_OK) return s;
   a.psi = (double2*)psi;
   a.work = (double2*)h->work;
-  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
   a.mode = 0;
   a.method = method_code(m);
   a.dt = dt;
@@ -695,6 +713,52 @@ gqd_status gqd_list_plans(int n, int* radices, int max_plans, int* count) {
   return GQD_OK;
 }
 
+gqd_status gqd_set_solve_log(gqd_handle* h, int* log, long long per_item) {
+  if (!h) return fail(GQD_ERR_INVALID, "NULL handle");
+  if (per_item < 0 || (per_item > 0 && !log)) return fail(GQD_ERR_INVALID, "solve log needs a buffer and a size >= 0");
+  h->solve_log = per_item > 0 ? log : nullptr;
+  h->log_cap = per_item > 0 ? per_item : 0;
+  // the kernels read each item's log from its statistics record (2D: both groups')
+  const int recs = h->dims == 2 ? 2 * h->batch : h->batch;
+  std::vector<ItemStats> st(recs);
+  GQD_HIP(hipDeviceSynchronize());
+  GQD_HIP(hipMemcpy(st.data(), h->d_stats, sizeof(ItemStats) * recs, hipMemcpyDeviceToHost));
+  for (int r = 0; r < recs; ++r) {
+    const int b = r % h->batch;
+    st[r].log = h->solve_log ? h->solve_log + (size_t)b * h->log_cap : nullptr;
+    st[r].log_cap = h->log_cap;
+  }
+  GQD_HIP(hipMemcpy(h->d_stats, st.data(), sizeof(ItemStats) * recs, hipMemcpyHostToDevice));
+  return GQD_OK;
+}
+
+gqd_status gqd_composition(gqd_scheme s, int order, double* tau, int max_tau, int* count) {
+  if (!count) return fail(GQD_ERR_INVALID, "NULL argument");
+  GammaTab gt;
+  gqd_status st = make_gammas(s, order, &gt);
+  if (st != GQD_OK) return st;
+  *count = gt.count;
+  if (!tau) return GQD_OK;
+  if (max_tau < gt.count) return fail(GQD_ERR_INVALID, "tau holds fewer than the substeps of one step");
+  static const double flat_tau[kFlatTauLen] = {GQD_FLAT_TAU_VALUES};
+  for (int c = 0; c < gt.count; ++c) {
+    if (gt.flat) {
+      tau[c] = flat_tau[gt.flat - 1 + c];
+      continue;
+    }
+    // the kernels' product, innermost level first (digit l of c picks level l's gamma)
+    double t = 1.0;
+    int cc = c;
+    for (int l = 0; l < gt.levels; ++l) {
+      const int d = cc % gt.arity;
+      cc /= gt.arity;
+      t = (d == gt.arity / 2 ? gt.mid[l] : gt.side[l]) * t;
+    }
+    tau[c] = t;
+  }
+  return GQD_OK;
+}
+
 gqd_status gqd_set_wait_limit(gqd_handle* h, int polls) {
   if (!h) return fail(GQD_ERR_INVALID, "NULL handle");
   if (polls < 0) return fail(GQD_ERR_INVALID, "wait limit must be >= 0");
@@ -736,7 +800,7 @@ gqd_status gqd_autotune(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, 
   if (s != GQD_OK) return s;
   a.psi = (double2*)psi;
   a.work = (double2*)h->work;
-  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
   a.mode = 0;
   a.method = (m == GQD_TRAP) ? kTrap : kMidp;
   a.dt = dt;
@@ -809,7 +873,7 @@ gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long
     a.aux = (double2*)lambda;
     a.gF = gF;
     a.work = (double2*)h->work;
-    a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+    a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
     a.dt = dt;
     a.nsteps = nsteps;
     hipStream_t strm = (hipStream_t)stream;
@@ -824,7 +888,7 @@ gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long
   a.aux = (double2*)lambda;
   a.gF = gF;
   a.work = (double2*)h->work;
-  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0};
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
   a.dt = dt;
   a.nsteps = nsteps;
   hipStream_t strm = (hipStream_t)stream;

@@ -134,6 +134,16 @@ __device__ __forceinline__ double opaque_d(double x) {
   asm volatile("" : "+s"(x));
   return x;
 }
+// Solve s of an item took `iters` Arnoldi iterations: written to the item's log when
+// the host set one (gqd_set_solve_log).  Called by one thread; reads the log pointer
+// from the item's statistics record at the time of use, so it holds no register.
+__device__ __forceinline__ void log_solve(ItemStats* st, long long s, int iters) {
+  if (!st) return;
+  const GQD_G ItemStats* p = opaque(st);
+  int* lg = p->log;
+  if (lg && s < p->log_cap) lg[s] = iters;
+}
+
 // A value every lane holds identically, made provably uniform (scalar register).
 __device__ __forceinline__ double uniform_d(double x) {
   const unsigned long long b = __double_as_longlong(x);

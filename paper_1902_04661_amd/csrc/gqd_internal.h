@@ -38,6 +38,12 @@ struct ItemStats {
   int max_iters;
   int failures;         // solves that hit maxit
   int nonfinite;        // 1 if a norm became NaN/Inf (the item stops there)
+  double max_resid;     // largest |b - X x| / |b| of a solve that ended on its true residual
+  // set by the host (gqd_set_solve_log), read by the kernels: the Arnoldi iterations of
+  // the item's solve s go to log[s] for s < log_cap (two-group reverse sweep: phi
+  // solves at even s, mu solves at odd s)
+  int* log;
+  long long log_cap;
 };
 
 struct SolveCfg {
@@ -45,16 +51,22 @@ struct SolveCfg {
   int m;        // restart length
   int maxit;    // iterations per solve
   int literal;  // 1: perform every explicit half-step
+  int verify;   // 1: a solve that converges by its residual estimate ends only once
+                // its true residual meets the tolerance (else GMRES restarts from x)
 };
 
 // Composition coefficients per recursion level l (raising order 2l+2 to 2l+4).  Both
 // schemes are symmetric with one distinct middle coefficient: triple jump
 // (g1, g2, g1), Suzuki (g1, g1, g3, g1, g1).  Digit d of a substep index selects
 // mid[l] when d == arity/2 and side[l] otherwise.
+// A non-recursive composition lists its substep fractions instead: flat > 0 is one
+// plus the offset of its first fraction in the device table of such lists, count its
+// length.
 struct GammaTab {
   int arity;    // 3 (triple jump) or 5 (Suzuki)
   int levels;   // order/2 - 1
-  int count;    // arity^levels substeps per step
+  int count;    // arity^levels substeps per step (flat: the length of the list)
+  int flat;     // 0: recursive; else 1 + offset of the list
   double side[kMaxLevels];
   double mid[kMaxLevels];
 };

@@ -6,6 +6,7 @@
 // the item's slice of the workspace.
 #include "gqd_device.hpp"
 #include "gqd_internal.h"
+#include "gqd_compositions.h"
 
 namespace gqd {
 
@@ -816,7 +817,11 @@ struct Eng {
 
 // composition fraction tau_c: product of one gamma per level, innermost level first
 // (the flattened list of Sec. II.D with gamma_1 applied first)
+// substep fractions of the non-recursive compositions (gqd_compositions.h)
+static __constant__ double kFlatTau[kFlatTauLen] = {GQD_FLAT_TAU_VALUES};
+
 __device__ __forceinline__ double substep_tau(int c, const GammaTab& gt) {
+  if (gt.flat) return kFlatTau[gt.flat - 1 + c];
   double t = 1.0;
   int cc = c;
   const int mid = gt.arity / 2;
@@ -926,6 +931,14 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
   const cplx* bg = nullptr;
   cplx* xg = nullptr;
   double al = 0.0, tolb = 0.0;
+  // thread 0 alone keeps the largest true relative residual a solve ended on, as a
+  // numerator/denominator pair (tol |r|, tol |b|; divided once at the end), in LDS:
+  // no register is held through the loop
+  GQD_L double* const max_resid = c.scal + 11;
+  if (threadIdx.x == 0) {
+    max_resid[0] = 0.0;
+    max_resid[1] = 1.0;
+  }
   int j = 0, iters = 0, after = kSubstep;
 
   int pc = kSubstep;
@@ -962,6 +975,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
     pc = kSolveGuess;
   };
   auto solve_end = [&](bool conv) {
+    if (threadIdx.x == 0) log_solve(a.stats ? a.stats + item : nullptr, solves, iters);
     ++solves;
     iters_total += iters;
     iters_sq += (long long)iters * iters;
@@ -1145,6 +1159,10 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           break;
         }
         if (beta <= tolb) {
+          if (threadIdx.x == 0 && tolb > 0.0 && a.sc.tol * beta * max_resid[1] > max_resid[0] * tolb) {
+            max_resid[0] = a.sc.tol * beta;
+            max_resid[1] = tolb;
+          }
           solve_end(true);
           break;
         }
@@ -1278,9 +1296,9 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           E::store(x, xg);
         }
         __syncthreads();  // y is read by all before it can be rewritten
-        if (cv) {
+        if (cv && !a.sc.verify) {
           solve_end(true);
-        } else {  // restart, or maxit / breakdown: the true residual decides
+        } else {  // verification, restart, or maxit / breakdown: the true residual decides
           request(xg, true);
           pc = kSolveResid;
         }
@@ -1409,6 +1427,7 @@ done:
     st->max_iters = max_iters;
     st->failures = failures;
     st->nonfinite = bad ? 1 : 0;
+    st->max_resid = max_resid[0] / max_resid[1];
   }
 }
 
@@ -1469,6 +1488,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
     st->max_iters = 0;
     st->failures = 0;
     st->nonfinite = 0;
+    st->max_resid = 0.0;
   }
 }
 

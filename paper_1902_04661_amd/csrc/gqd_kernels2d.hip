@@ -20,6 +20,7 @@
 // so all workgroups are resident.
 #include "gqd_device.hpp"
 #include "gqd_internal.h"
+#include "gqd_compositions.h"
 
 namespace gqd {
 
@@ -443,7 +444,11 @@ enum Pc2 {
   k2Inner
 };
 
+// substep fractions of the non-recursive compositions (gqd_compositions.h)
+static __constant__ double kFlatTau2[kFlatTauLen] = {GQD_FLAT_TAU_VALUES};
+
 __device__ __forceinline__ double substep_tau2(int cc, const GammaTab& gt) {
+  if (gt.flat) return kFlatTau2[gt.flat - 1 + cc];
   double t = 1.0;
   const int mid = gt.arity / 2;
 #pragma unroll
@@ -541,7 +546,8 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   LineReq rq{};
   const cplx* bg = nullptr;
   cplx* xg = nullptr;
-  double al = 0.0, tolb = 0.0;
+  double al = 0.0, tolb = 0.0, bnrm = 0.0;
+  double max_resid = 0.0;  // largest true relative residual a solve ended on
   int j = 0, iters = 0, after = k2Substep;
   int pc = k2Substep;
   // Arnoldi runs on H - s, s the Rayleigh quotient of the first basis vector of the
@@ -585,11 +591,15 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
     const double bnorm = sqrt(uniform_d(c.red[0]));
     if (!isfinite(bnorm)) bad = true;
     tolb = a.sc.tol * bnorm;
+    bnrm = bnorm;
     request(b, true);
     pc = k2SolveGuess;
     return true;
   };
   auto solve_end = [&](bool conv) {
+    // the two groups of a reverse sweep interleave: phi solves even, mu solves odd
+    if (g == 0 && threadIdx.x == 0)
+      log_solve(a.stats ? a.stats + item : nullptr, R == 2 ? 2LL * solves + role : (long long)solves, iters);
     ++solves;
     iters_total += iters;
     iters_sq += (long long)iters * iters;
@@ -760,6 +770,8 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
           break;
         }
         if (beta <= tolb) {
+          const double rr = bnrm > 0.0 ? beta / bnrm : 0.0;
+          if (rr > max_resid) max_resid = rr;
           solve_end(true);
           break;
         }
@@ -888,9 +900,9 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
             if (eb + u * T < e1) xg[eb + u * T] = x[u];
         }
         touched = true;
-        if (cv) {
+        if (cv && !a.sc.verify) {
           solve_end(true);
-        } else {
+        } else {  // verification, restart, or maxit / breakdown: the true residual decides
           request(xg, true);
           pc = k2SolveResid;
         }
@@ -1046,6 +1058,7 @@ done:
     st->max_iters = max_iters;
     st->failures = failures;
     st->nonfinite = aborted ? 2 : (bad ? 1 : 0);
+    st->max_resid = max_resid;
   }
 }
 

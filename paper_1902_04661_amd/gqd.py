@@ -23,11 +23,12 @@ TRAP, MIDP = 0, 1
 EULER_EXPLICIT, EULER_IMPLICIT, SOD = 2, 3, 4
 # the diabatic split-operator method (Table I): the surfaces are read as W11, W22, W12
 SPLIT_OPERATOR = 5
-TRIPLE_JUMP, SUZUKI = 0, 1
+TRIPLE_JUMP, SUZUKI, OPTIMAL = 0, 1, 2
 _METHODS = {"trap": TRAP, "midp": MIDP, "euler_explicit": EULER_EXPLICIT,
             "euler_implicit": EULER_IMPLICIT, "sod": SOD, "split_operator": SPLIT_OPERATOR}
 _METHODS.update({v: v for v in list(_METHODS.values())})
-_SCHEMES = {"triple_jump": TRIPLE_JUMP, "suzuki": SUZUKI, TRIPLE_JUMP: TRIPLE_JUMP, SUZUKI: SUZUKI}
+_SCHEMES = {"triple_jump": TRIPLE_JUMP, "suzuki": SUZUKI, "optimal": OPTIMAL,
+            TRIPLE_JUMP: TRIPLE_JUMP, SUZUKI: SUZUKI, OPTIMAL: OPTIMAL}
 SIZES = (256, 512, 1024, 2048, 4096)
 
 STATUS = {0: "OK", -1: "INVALID", -2: "HIP", -3: "NOMEM", -4: "NOT_CONVERGED",
@@ -52,7 +53,7 @@ class _GridDesc(ctypes.Structure):
 
 class _SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
-                ("literal", ctypes.c_int)]
+                ("literal", ctypes.c_int), ("verify", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -60,7 +61,8 @@ class _Stats(ctypes.Structure):
                 ("iterations_sq", ctypes.c_longlong),
                 ("solves", ctypes.c_longlong), ("max_iters", ctypes.c_int),
                 ("failures", ctypes.c_int), ("failed_item", ctypes.c_int),
-                ("nonfinite", ctypes.c_int), ("alg_bytes", ctypes.c_double)]
+                ("nonfinite", ctypes.c_int), ("alg_bytes", ctypes.c_double),
+                ("max_true_resid", ctypes.c_double)]
 
 
 _lib = None
@@ -93,6 +95,8 @@ def load_library(path: str = LIB_PATH):
         "gqd_list_plans": ([i, vp, i, ctypes.POINTER(i)], i),
         "gqd_set_plan": ([vp, i, vp], i),
         "gqd_set_wait_limit": ([vp, i], i),
+        "gqd_set_solve_log": ([vp, vp, ll], i),
+        "gqd_composition": ([i, i, vp, i, ctypes.POINTER(i)], i),
         "gqd_diag": ([vp, vp, vp, vp], i),
         "gqd_inner": ([vp, vp, vp, vp, vp], i),
         "gqd_last_error": ([], ctypes.c_char_p),
@@ -109,7 +113,7 @@ def exported_symbols() -> List[str]:
     return ["gqd_create", "gqd_destroy", "gqd_state_size", "gqd_state_offset",
             "gqd_workspace_size", "gqd_set_workspace", "gqd_set_surfaces", "gqd_apply_H",
             "gqd_implicit_step", "gqd_propagate", "gqd_propagate_items", "gqd_adjoint", "gqd_autotune",
-            "gqd_list_plans", "gqd_set_plan", "gqd_set_wait_limit",
+            "gqd_list_plans", "gqd_set_plan", "gqd_set_wait_limit", "gqd_set_solve_log", "gqd_composition",
             "gqd_diag", "gqd_inner",
             "gqd_last_error"]
 
@@ -128,9 +132,11 @@ class SolverOpts:
     restart: int = 32
     maxit: int = 1000
     literal: bool = False
+    verify: bool = False  # end a solve only on a true residual within tol (restart otherwise)
 
     def c(self) -> _SolverOpts:
-        return _SolverOpts(float(self.tol), int(self.restart), int(self.maxit), int(bool(self.literal)))
+        return _SolverOpts(float(self.tol), int(self.restart), int(self.maxit), int(bool(self.literal)),
+                           int(bool(self.verify)))
 
 
 @dataclass
@@ -144,13 +150,14 @@ class Stats:
     failed_item: int
     nonfinite: int
     alg_bytes: float
+    max_true_resid: float
 
 
 def _stats(st) -> Optional[Stats]:
     if st is None:
         return None
     return Stats(st.h_applies, st.iterations, st.iterations_sq, st.solves, st.max_iters,
-                 st.failures, st.failed_item, st.nonfinite, st.alg_bytes)
+                 st.failures, st.failed_item, st.nonfinite, st.alg_bytes, st.max_true_resid)
 
 
 def _stream_ptr(stream=None):
@@ -165,6 +172,16 @@ def list_plans(n: int) -> List[tuple]:
     cnt = ctypes.c_int()
     _check(_lib.gqd_list_plans(int(n), buf, 16, ctypes.byref(cnt)))
     return [tuple(buf[4 * k + i] for i in range(4)) for k in range(cnt.value)]
+
+
+def composition(scheme, order: int) -> np.ndarray:
+    """Substep fractions tau_c of one composed step, in order of application."""
+    load_library()
+    cnt = ctypes.c_int()
+    _check(_lib.gqd_composition(_SCHEMES[scheme], int(order), None, 0, ctypes.byref(cnt)))
+    buf = (ctypes.c_double * cnt.value)()
+    _check(_lib.gqd_composition(_SCHEMES[scheme], int(order), buf, cnt.value, ctypes.byref(cnt)))
+    return np.array(buf[:], dtype=np.float64)
 
 
 class Propagator:
@@ -210,6 +227,7 @@ class Propagator:
         self.shapes = shapes
         self._work = None
         self._work_m = -1
+        self._log = None
         self.V = None
         self.F = None
         self._pending_surfaces = (V, F)
@@ -220,7 +238,27 @@ class Propagator:
         if V is not None and F is not None:
             self.set_surfaces(V, F)
 
+    def close(self) -> None:
+        """Destroy the handle now (device tables, side streams and events), with the HIP
+        runtime still up.  Waits for the device first.  Later calls raise."""
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            torch.cuda.synchronize(self.device)
+            _lib.gqd_destroy(h)
+        self._h = None
+        self._work = None
+        self._log = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
+        # a handle that was never closed is freed here; at interpreter exit the library
+        # may already be gone, so close() is the dependable way
         try:
             if getattr(self, "_h", None) is not None and _lib is not None:
                 _lib.gqd_destroy(self._h)
@@ -315,6 +353,25 @@ class Propagator:
         """Use the transform plan with these radices for items of size n."""
         r = (ctypes.c_int * 4)(*[int(x) for x in radices])
         _check(_lib.gqd_set_plan(self._h, int(n), r))
+
+    def set_solve_log(self, per_item: int) -> None:
+        """Record the Arnoldi iteration count of each of the first per_item solves of
+        every item in later calls (0 switches the record off); read it with solve_log()."""
+        if per_item > 0:
+            self._log = torch.full((self.batch, int(per_item)), -1, dtype=torch.int32, device=self.device)
+            _check(_lib.gqd_set_solve_log(self._h, ctypes.c_void_p(self._log.data_ptr()), int(per_item)))
+        else:
+            _check(_lib.gqd_set_solve_log(self._h, None, 0))
+            self._log = None
+
+    def solve_log(self, clear: bool = True) -> np.ndarray:
+        """(batch, per_item) iteration counts of the last calls' solves (-1: no solve)."""
+        if self._log is None:
+            raise ValueError("no solve log set (set_solve_log)")
+        out = self._log.cpu().numpy().copy()
+        if clear:
+            self._log.fill_(-1)
+        return out
 
     def set_wait_limit(self, polls: int) -> None:
         """Polls a 2D grid wait makes before the item gives up (0: the default)."""

@@ -129,21 +129,26 @@ def test_full_size_step_matches_oracle_2d(gqd):
     assert r <= 1e-12
 
 
+def oracle_forward(it, scheme, order, dt, nsteps, opts):
+    """The oracle's forward run and its loss gradient dL/dpsi*(T) = dv Pi_2 psi(T): both
+    reverse sweeps start from these."""
+    m = O.model_from_item(it)
+    oT = O.propagate(m, it.psi0, O.MIDP, scheme, order, dt, nsteps, O.SolverOpts(**opts))
+    return m, oT, O.population_loss(m, oT)[1]
+
+
 def test_adjoint_matches_oracle_2d(gqd):
     it = moving_item(64)
     prop = gqd.from_items([it])
-    m = O.model_from_item(it)
     opts = dict(tol=1e-15, restart=32)
-    psi = prop.pack([it.psi0])
-    prop.propagate(psi, "midp", "suzuki", 4, 10.0, 3, gqd.SolverOpts(**opts))
-    psiT = prop.unpack(psi)[0]
-    _, lamT = O.population_loss(m, psiT)
-    lam = prop.pack([lamT])
+    m, oT, lT = oracle_forward(it, O.SUZUKI, 4, 10.0, 3, opts)
+    psi = prop.pack([oT])
+    lam = prop.pack([lT])
     gF = torch.zeros(prop.f_size, dtype=torch.float64, device=psi.device)
     st = prop.adjoint(psi, lam, gF, "suzuki", 4, 10.0, 3, gqd.SolverOpts(**opts))
     # phi and mu are solved by two groups of workgroups; the statistics count both
     assert st.solves == 2 * 5 * 3 and st.failures == 0 and st.nonfinite == 0
-    po, lo, go = O.adjoint(m, psiT, lamT, O.SUZUKI, 4, 10.0, 3, O.SolverOpts(**opts))
+    po, lo, go = O.adjoint(m, oT, lT, O.SUZUKI, 4, 10.0, 3, O.SolverOpts(**opts))
     rl = rel(prop.unpack(lam)[0], lo)
     rg0 = rel(gF.cpu().numpy()[:64 * 64], go[0].ravel())
     rg1 = rel(gF.cpu().numpy()[64 * 64:], go[1].ravel())
@@ -159,25 +164,49 @@ def test_adjoint_batch_of_2d_items_matches_oracle(gqd):
     items = [moving_item(64, seed=s, p0=(1.0 + s, -0.5 * s)) for s in (2, 3, 4)]
     prop = gqd.from_items(items)
     opts = dict(tol=1e-15, restart=32)
-    psi = prop.pack([it.psi0 for it in items])
-    prop.propagate(psi, "midp", "suzuki", 2, 10.0, 3, gqd.SolverOpts(**opts))
-    lamT = []
-    for it, pT in zip(items, prop.unpack(psi)):
-        lamT.append(O.population_loss(O.model_from_item(it), pT)[1])
-    refs = [O.adjoint(O.model_from_item(it), pT, lT, O.SUZUKI, 2, 10.0, 3, O.SolverOpts(**opts))
-            for it, pT, lT in zip(items, prop.unpack(psi), lamT)]
-    lam = prop.pack(lamT)
+    fwd = [oracle_forward(it, O.SUZUKI, 2, 10.0, 3, opts) for it in items]
+    psi = prop.pack([f[1] for f in fwd])
+    lam = prop.pack([f[2] for f in fwd])
     gF = torch.zeros(prop.f_size, dtype=torch.float64, device=psi.device)
     st = prop.adjoint(psi, lam, gF, "suzuki", 2, 10.0, 3, gqd.SolverOpts(**opts))
     assert st.solves == 3 * 2 * 1 * 3 and st.failures == 0 and st.nonfinite == 0
     g = gF.cpu().numpy().reshape(3, 2, 64 * 64)
-    for b, (it, lo_ref, out_lam, out_psi) in enumerate(zip(items, refs, prop.unpack(lam), prop.unpack(psi))):
-        po, lo, go = lo_ref
+    for b, (it, (m, oT, lT), out_lam, out_psi) in enumerate(zip(items, fwd, prop.unpack(lam), prop.unpack(psi))):
+        po, lo, go = O.adjoint(m, oT, lT, O.SUZUKI, 2, 10.0, 3, O.SolverOpts(**opts))
         rl, rp = rel(out_lam, lo), rel(out_psi, it.psi0)
         rg = max(rel(g[b, 0], go[0].ravel()), rel(g[b, 1], go[1].ravel()))
         print(f"2D adjoint batch item {b}: lambda rel {rl:.2e}, gF rel {rg:.2e}, psi(0) rel {rp:.2e}",
               flush=True)
         assert rl <= 1e-10 and rg <= 1e-10 and rp <= 2e-12
+
+
+def test_adjoint_matches_oracle_full_size_2d(gqd):
+    # the 256 x 256 model of the 2D gradient workload: one Suzuki order-4 step, then its
+    # reverse sweep on two groups of 64 workgroups each (phi and mu) with the hand-offs
+    # between them, from the oracle's psi(T) and loss gradient
+    it = I.two_dim_item(256, 256)
+    n = 256
+    prop = gqd.from_items([it])
+    opts = dict(tol=1e-14, restart=32)
+    m, oT, lT = oracle_forward(it, O.SUZUKI, 4, 10.0, 1, opts)
+    psi = prop.pack([it.psi0])
+    prop.propagate(psi, "midp", "suzuki", 4, 10.0, 1, gqd.SolverOpts(**opts))
+    print(f"2D 256x256 forward: psi(T) rel {rel(prop.unpack(psi)[0], oT):.2e}", flush=True)
+    psi = prop.pack([oT])
+    lam = prop.pack([lT])
+    gF = torch.zeros(prop.f_size, dtype=torch.float64, device=psi.device)
+    st = prop.adjoint(psi, lam, gF, "suzuki", 4, 10.0, 1, gqd.SolverOpts(**opts))
+    assert st.solves == 2 * 5 and st.failures == 0 and st.nonfinite == 0
+    po, lo, go = O.adjoint(m, oT, lT, O.SUZUKI, 4, 10.0, 1, O.SolverOpts(**opts))
+    g = gF.cpu().numpy()
+    rl = rel(prop.unpack(lam)[0], lo)
+    rg0 = rel(g[:n * n], go[0].ravel())
+    rg1 = rel(g[n * n:], go[1].ravel())
+    rp = rel(prop.unpack(psi)[0], it.psi0)
+    print(f"2D 256x256 adjoint: lambda rel {rl:.2e}, gF_1 rel {rg0:.2e}, gF_2 rel {rg1:.2e}, "
+          f"psi(0) rel {rp:.2e} (oracle {rel(po, it.psi0):.2e}), {st.iterations} iterations in "
+          f"{st.solves} solves", flush=True)
+    assert rl <= 1e-10 and rg0 <= 1e-10 and rg1 <= 1e-10 and rp <= 2e-12
 
 
 def test_wait_limit_gives_up_and_recovers_2d(gqd):
