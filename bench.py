@@ -1,23 +1,26 @@
 """Benchmark: grid-point.steps/s of 8th-order composed implicit midpoint at the step
 that reaches convergence error 1e-10, on one MI355X.
 
-Workload.  The two-surface NaI-like adiabatic model on N = 2048 points of [3, 16) bohr
-(Morse + repulsive surfaces, Gaussian coupling), Suzuki-fractal composition of the
-implicit midpoint method to order 8 (125 substeps per step), step dt = 10 a.u. (the
-largest dt_k = 40 * 2^-k whose error at T = 4000 a.u. against the dt/8 order-8
-reference is <= 1e-10; see paper_1902_04661_amd.convergence), GMRES tolerance 1e-14.
-That packet (q0 = 5, p0 = 0, width 0.12, coupling amplitude 0.4 at q = 7), the one the
-step-size sweep was run on, is replicated B times to fill the GPU (weak scaling by
-batch); one "step" advances every copy by dt in one kernel launch.  One packet alone is
-timed too (single_packet), and a seeded ragged batch of different packets and sizes
-(ragged_batch).
+Workload.  1024 seeded draws of the two-surface NaI-like adiabatic model on N = 2048
+points of [3, 16) bohr (Morse + repulsive surfaces, Gaussian coupling): packet centre
+q0 ~ U[4.5, 6], momentum p0 ~ U[-5, 5], coupling amplitude ~ U[0.1, 0.8], width 0.12 (the
+ragged batch's draws on one grid size).  Suzuki-fractal composition of the implicit
+midpoint method to order 8 (125 substeps per step) at dt = 20 a.u.: the largest
+dt_k = 40 * 2^-k whose convergence error at T = 4000 a.u. stays <= 1e-10 for the six
+highest-energy draws of this batch (6.2e-11 at 20 a.u., 1.4e-8 at 40 a.u.; see
+paper_1902_04661_amd.convergence), every system solved to stagnation (GMRES tolerance
+1e-17), as in that sweep.  One "step" advances every packet by dt in one kernel launch.
+Side legs: the 8th-order triple jump on the same batch at its own 1e-10 step
+(0.625 a.u.), one packet alone, the 4096-packet ragged batch (N in 256..4096, Suzuki
+order 6 at its verified step 2.5 a.u.), 1D and 2D gradients, the 2D model, the
+elementary and diabatic controls.
 
 Roofline: the propagation kernel against the HBM peak (8 TB/s) with algorithmic bytes
 32 (I^2 + 4I + 8) per grid point per substep for a solve of I Arnoldi iterations
 (S = 2 complex128 vectors, one Gram-Schmidt pass, fused H application), summed over
 the solves of one launch and divided by the launch's average duration (HIP events
-on the launch stream).  cpu_baseline: the CPU oracle timed on one host core over a
-bounded sample of the same workload.
+on the launch stream).  cpu_baseline: the CPU oracle on draws of the same batch, one
+packet per process on the host's cores, over a bounded sample.
 """
 from __future__ import annotations
 
@@ -34,10 +37,19 @@ if ROOT not in sys.path:
 
 METRIC = "grid-point·steps/s at 1e-10 error, 8th order; adjoint grads/s; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-DT_STAR = 10.0
 N = 2048
+BATCH = 1024
 ORDER, SCHEME, METHOD = 8, "suzuki", "midp"
-TOL = 1e-14
+# the step-size sweep's results for this batch (Suzuki and triple jump, order 8) and its
+# solve tolerance; the ragged batch's step is verified by tests/test_gpu_step_verification
+DT_STAR = 20.0
+DT_STAR_TJ = 0.625
+TOL = 1e-17
+RAGGED_DT = 2.5
+# the 2D model and the 1D gradient workload run at their configurations' own steps
+DT_2D = 10.0
+TOL_2D = 1e-14
+TOL_ADJ = 1e-14
 
 # Memory traffic of the propagation kernel from two rocprofv3 --pmc passes (FETCH_SIZE, then
 # WRITE_SIZE) over one launch from t = 0 of this workload, scaled by what the counters read
@@ -78,50 +90,85 @@ def alg_bytes(n: int, st) -> float:
     return 32.0 * n * (st.iterations_sq + 4 * st.iterations + 8 * st.solves)
 
 
-def ragged_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
-    """Ragged batch: seeded N in {256..4096}, centres, momenta, amplitudes; Suzuki order 6,
-    dt = 10 a.u.; one launch per grid size on forked streams per step."""
+def timed_launches(prop, psi, steps, method, scheme, order, dt, opts):
+    """`steps` launches of one composed step each, timed with HIP events on the launch
+    stream; returns (average launch seconds, wall seconds, summed statistics)."""
     import torch
-    items = inputs.ragged_batch(batch, seed=0)
-    prop = gqd.from_items(items, device=dev)
-    psi = prop.pack([it.psi0 for it in items])
-    opts = gqd.SolverOpts(tol=TOL, restart=32)
-    prop.propagate(psi, METHOD, SCHEME, 6, DT_STAR, 1, opts)
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    tot = dict(bytes=0.0, iterations=0, iterations_sq=0, solves=0, h_applies=0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    byts = 0.0
-    for _ in range(steps):
-        st = prop.propagate(psi, METHOD, SCHEME, 6, DT_STAR, 1, opts)
-        byts += st.alg_bytes
+    for k in range(steps):
+        starts[k].record(stream)
+        st = prop.propagate(psi, method, scheme, order, dt, 1, opts)   # one launch
+        ends[k].record(stream)
+        tot["bytes"] += st.alg_bytes
+        for key in ("iterations", "iterations_sq", "solves", "h_applies"):
+            tot[key] += getattr(st, key)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    wall = time.perf_counter() - t0
+    kern = sum(a.elapsed_time(b) for a, b in zip(starts, ends)) / steps / 1e3
+    return kern, wall, tot
+
+
+def ragged_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
+    """Ragged batch: seeded N in {256..4096}, centres, momenta, amplitudes; Suzuki order 6
+    at its verified step; one launch per grid size on forked streams per step."""
+    import torch
+    items = inputs.ragged_batch(batch, seed=0)
+    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    with gqd.from_items(items, device=dev) as prop:
+        psi = prop.pack([it.psi0 for it in items])
+        prop.propagate(psi, METHOD, SCHEME, 6, RAGGED_DT, 1, opts)
+        kern, wall, tot = timed_launches(prop, psi, steps, METHOD, SCHEME, 6, RAGGED_DT, opts)
     pts = int(sum(it.n for it in items))
-    return {"value": pts * steps / el, "unit": "grid-point·steps/s", "ms_per_step": 1e3 * el / steps,
-            "alg_GBps": byts / el / 1e9, "hbm_frac": byts / el / 1e9 / HBM_PEAK_GBS,
-            "workload": f"{batch} packets, N in {{256..4096}} (sum {pts}), Suzuki order 6, dt={DT_STAR}"}
+    return {"value": pts * steps / wall, "unit": "grid-point·steps/s", "ms_per_step": 1e3 * wall / steps,
+            "alg_GBps": tot["bytes"] / wall / 1e9, "hbm_frac": tot["bytes"] / wall / 1e9 / HBM_PEAK_GBS,
+            "mean_gmres_iterations": tot["iterations"] / max(tot["solves"], 1),
+            "workload": f"{batch} packets, N in {{256..4096}} (sum {pts}), Suzuki order 6, dt={RAGGED_DT}, "
+                        f"GMRES tol {TOL:g}"}
+
+
+def triple_jump_leg(gqd, inputs, dev, items, steps: int) -> dict:
+    """The same drawn batch under the 8th-order triple jump (27 substeps per step) at its
+    own 1e-10 step: throughput per step and, comparable across schemes, simulated
+    time per second (a.u./s) against the Suzuki run."""
+    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    with gqd.from_items(items, device=dev) as prop:
+        psi = prop.pack([it.psi0 for it in items])
+        prop.propagate(psi, METHOD, "triple_jump", ORDER, DT_STAR_TJ, 1, opts)
+        kern, wall, tot = timed_launches(prop, psi, steps, METHOD, "triple_jump", ORDER, DT_STAR_TJ, opts)
+    return {"value": len(items) * N * steps / wall, "unit": "grid-point·steps/s",
+            "ms_per_step": 1e3 * wall / steps, "simulated_au_per_s": DT_STAR_TJ * steps / wall,
+            "mean_gmres_iterations": tot["iterations"] / max(tot["solves"], 1),
+            "alg_GBps": tot["bytes"] / steps / kern / 1e9,
+            "workload": f"{len(items)} drawn packets, N={N}, triple jump order 8, dt={DT_STAR_TJ}, "
+                        f"GMRES tol {TOL:g}"}
 
 
 SOD_DT = 0.15  # below 1 / E_max of the N = 2048 grid on [3, 16) (E_max ~ 4.3 Ha)
 
 
 def elementary_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
-    """Second-order differencing (Eq. 16) on the benchmark's packet replicated `batch`
-    times, at the largest round step below its stability limit.  One H application per
-    step and grid point; algorithmic traffic 128 bytes per grid point per step (read
-    psi(t) and psi(t - dt), write psi(t + dt) and the new previous state)."""
+    """Second-order differencing (Eq. 16) on the resting packet replicated `batch` times,
+    at the largest round step below its stability limit.  One H application per step and
+    grid point; algorithmic traffic 128 bytes per grid point per step (read psi(t) and
+    psi(t - dt), write psi(t + dt) and the new previous state)."""
     import torch
     it = inputs.nai_like_item(N)
-    prop = gqd.from_items([it] * batch, device=dev)
-    psi = prop.pack([it.psi0] * batch)
-    prop.propagate(psi, "sod", "suzuki", 2, SOD_DT, 2, stats=False)
-    s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(s)
-    prop.propagate(psi, "sod", "suzuki", 2, SOD_DT, steps, stats=False)
-    e1.record(s)
-    torch.cuda.synchronize()
-    el = e0.elapsed_time(e1) * 1e-3
+    with gqd.from_items([it] * batch, device=dev) as prop:
+        psi = prop.pack([it.psi0] * batch)
+        prop.propagate(psi, "sod", "suzuki", 2, SOD_DT, 2, stats=False)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        prop.propagate(psi, "sod", "suzuki", 2, SOD_DT, steps, stats=False)
+        e1.record(s)
+        torch.cuda.synchronize()
+        el = e0.elapsed_time(e1) * 1e-3
     gps = batch * N * steps / el
     return {"value": gps, "unit": "grid-point·steps/s", "ms_per_step": 1e3 * el / steps,
             "us_per_h_apply_per_packet": 1e6 * el * 256 / (batch * (steps + 1)),
@@ -138,21 +185,22 @@ def split_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
     from paper_1902_04661_amd import diabatic
     d = inputs.diabatic_crossing_item(N)
     ad, _ = diabatic.adiabatic_item(d)
-    out = {"workload": f"diabatic crossing model, {batch} x N={N}, Suzuki order {ORDER}, dt={DT_STAR}"}
+    dt = 10.0
+    out = {"workload": f"diabatic crossing model, {batch} x N={N}, Suzuki order {ORDER}, dt={dt}, GMRES tol 1e-14"}
     s = torch.cuda.current_stream()
     for name, item, method, nsteps in (("split_operator", diabatic.diabatic_as_surfaces(d), "split_operator", steps),
                                        ("adiabatic_midpoint", ad, METHOD, 1)):
-        prop = gqd.from_items([item] * batch, device=dev)
-        psi = prop.pack([item.psi0] * batch)
-        opts = gqd.SolverOpts(tol=TOL, restart=32)
-        prop.propagate(psi, method, SCHEME, ORDER, DT_STAR, 1, opts, stats=False)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(s)
-        prop.propagate(psi, method, SCHEME, ORDER, DT_STAR, nsteps, opts, stats=False)
-        e1.record(s)
-        torch.cuda.synchronize()
-        el = e0.elapsed_time(e1) * 1e-3
+        with gqd.from_items([item] * batch, device=dev) as prop:
+            psi = prop.pack([item.psi0] * batch)
+            opts = gqd.SolverOpts(tol=1e-14, restart=32)
+            prop.propagate(psi, method, SCHEME, ORDER, dt, 1, opts, stats=False)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(s)
+            prop.propagate(psi, method, SCHEME, ORDER, dt, nsteps, opts, stats=False)
+            e1.record(s)
+            torch.cuda.synchronize()
+            el = e0.elapsed_time(e1) * 1e-3
         out[name] = {"value": batch * N * nsteps / el, "unit": "grid-point·steps/s",
                      "ms_per_step": 1e3 * el / nsteps}
     out["split_over_adiabatic"] = out["split_operator"]["value"] / out["adiabatic_midpoint"]["value"]
@@ -164,18 +212,18 @@ def twod_leg(gqd, inputs, dev, steps: int) -> dict:
     implicit midpoint, dt = 10 a.u.: one item shared by a group of workgroups."""
     import torch
     it = inputs.two_dim_item(256, 256)
-    prop = gqd.from_items([it], device=dev)
-    psi = prop.pack([it.psi0])
-    opts = gqd.SolverOpts(tol=TOL, restart=32)
-    prop.propagate(psi, METHOD, SCHEME, ORDER, DT_STAR, 1, opts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = prop.propagate(psi, METHOD, SCHEME, ORDER, DT_STAR, steps, opts)
-    el = time.perf_counter() - t0
+    opts = gqd.SolverOpts(tol=TOL_2D, restart=32)
+    with gqd.from_items([it], device=dev) as prop:
+        psi = prop.pack([it.psi0])
+        prop.propagate(psi, METHOD, SCHEME, ORDER, DT_2D, 1, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = prop.propagate(psi, METHOD, SCHEME, ORDER, DT_2D, steps, opts)
+        el = time.perf_counter() - t0
     return {"value": 256 * 256 * steps / el, "unit": "grid-point·steps/s", "ms_per_step": 1e3 * el / steps,
             "mean_gmres_iterations": st.iterations / max(st.solves, 1),
             "us_per_h_apply": 1e6 * el / max(st.h_applies, 1), "alg_GBps": st.alg_bytes / el / 1e9,
-            "workload": f"2D 256x256, Suzuki order 8 midpoint, dt={DT_STAR}, {steps} steps"}
+            "workload": f"2D 256x256, Suzuki order 8 midpoint, dt={DT_2D}, {steps} steps, GMRES tol {TOL_2D:g}"}
 
 
 def adjoint2d_leg(gqd, inputs, dev, nsteps: int) -> dict:
@@ -184,30 +232,29 @@ def adjoint2d_leg(gqd, inputs, dev, nsteps: int) -> dict:
     import torch
     from paper_1902_04661_amd import autograd as ag
     it = inputs.two_dim_item(256, 256)
-    prop = gqd.from_items([it], device=dev)
     Q = ag.grid2d(256, it.qmin, it.qmax, dev)
     P = [torch.tensor(v, dtype=torch.float64, device=dev, requires_grad=True) for v in it.params["cparams"]]
-    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    opts = gqd.SolverOpts(tol=TOL_2D, restart=32)
     dv = ((it.qmax[0] - it.qmin[0]) / 256) * ((it.qmax[1] - it.qmin[1]) / 256)
+    with gqd.from_items([it], device=dev) as prop:
+        def gradient(steps):
+            F = ag.coupling_2d(Q[0], Q[1], *P).reshape(-1)
+            psiT = ag.propagate(prop, prop.pack([it.psi0]), F, "suzuki", 8, DT_2D, steps, opts)
+            L = ag.surface_population(psiT.reshape(2, 256, 256), dv)
+            L.backward()
+            return L
 
-    def gradient(steps):
-        F = ag.coupling_2d(Q[0], Q[1], *P).reshape(-1)
-        psiT = ag.propagate(prop, prop.pack([it.psi0]), F, "suzuki", 8, DT_STAR, steps, opts)
-        L = ag.surface_population(psiT.reshape(2, 256, 256), dv)
-        L.backward()
-        return L
-
-    gradient(1)  # warm-up: workspace, kernel loading, autograd set-up
-    for p in P:
-        p.grad = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    L = gradient(nsteps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+        gradient(1)  # warm-up: workspace, kernel loading, autograd set-up
+        for p in P:
+            p.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = gradient(nsteps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
     return {"value": 1.0 / el, "unit": "gradients/s", "params_per_gradient": 4, "seconds": el,
             "loss": float(L.detach()), "grad": [float(p.grad) for p in P],
-            "workload": f"2D 256x256, Suzuki order 8, dt={DT_STAR}, {nsteps} steps, forward + reverse"}
+            "workload": f"2D 256x256, Suzuki order 8, dt={DT_2D}, {nsteps} steps, forward + reverse"}
 
 
 def adjoint_leg(gqd, inputs, dev, batch: int, nsteps: int) -> dict:
@@ -216,67 +263,81 @@ def adjoint_leg(gqd, inputs, dev, batch: int, nsteps: int) -> dict:
     import torch
     from paper_1902_04661_amd import autograd as ag
     items = inputs.adjoint_batch(batch, seed=1, n=1024)
-    prop = gqd.from_items(items, device=dev)
     q = ag.grid(1024, items[0].qmin, items[0].qmax, dev)
     P = {k: torch.tensor([it.params[k] for it in items], dtype=torch.float64, device=dev, requires_grad=True)
          for k in ["q0", "p0", "width", "amp", "center"]}
-    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    opts = gqd.SolverOpts(tol=TOL_ADJ, restart=32)
+    with gqd.from_items(items, device=dev) as prop:
+        def gradient(steps):
+            psi0 = ag.gaussian_packets(q, P["q0"], P["p0"], P["width"]).reshape(-1)
+            F = ag.couplings(q, P["amp"], P["center"]).reshape(-1)
+            psiT = ag.propagate(prop, psi0, F, "suzuki", 4, 4.0, steps, opts)
+            L = (items[0].dq * torch.abs(psiT.reshape(batch, 2, 1024)[:, 1]) ** 2).sum()
+            L.backward()
+            return psi0
 
-    def gradient(steps):
-        psi0 = ag.gaussian_packets(q, P["q0"], P["p0"], P["width"]).reshape(-1)
-        F = ag.couplings(q, P["amp"], P["center"]).reshape(-1)
-        psiT = ag.propagate(prop, psi0, F, "suzuki", 4, 4.0, steps, opts)
-        L = (items[0].dq * torch.abs(psiT.reshape(batch, 2, 1024)[:, 1]) ** 2).sum()
-        L.backward()
-        return psi0
-
-    gradient(1)  # warm-up: workspace, kernel loading, autograd set-up
-    for v in P.values():
-        v.grad = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    psi0 = gradient(nsteps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    # the plain forward solve of the same packets at the same tolerance, for comparison
-    psi = psi0.detach().clone()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prop.propagate(psi, "midp", "suzuki", 4, 4.0, nsteps, opts, stats=False)
-    torch.cuda.synchronize()
-    fwd = time.perf_counter() - t1
+        gradient(1)  # warm-up: workspace, kernel loading, autograd set-up
+        for v in P.values():
+            v.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        psi0 = gradient(nsteps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        # the plain forward solve of the same packets at the same tolerance, for comparison
+        psi = psi0.detach().clone()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prop.propagate(psi, "midp", "suzuki", 4, 4.0, nsteps, opts, stats=False)
+        torch.cuda.synchronize()
+        fwd = time.perf_counter() - t1
     return {"value": batch / el, "unit": "gradients/s", "params_per_gradient": 5, "seconds": el,
             "forward_only_seconds": fwd, "gradient_over_forward": el / fwd,
-            "workload": f"{batch} packets, N=1024, Suzuki order 4, dt=4, {nsteps} steps, forward + reverse"}
+            "workload": f"{batch} packets, N=1024, Suzuki order 4, dt=4, {nsteps} steps, forward + reverse, "
+                        f"GMRES tol {TOL_ADJ:g}"}
 
 
-def cpu_leg(seconds: float = 15.0) -> dict:
-    """Oracle on one core: the first packet of the batch, SZ-8 steps of dt* until ~seconds."""
-    code = f"""
+CPU_PACKET = """
 import sys, time, json
-sys.path.insert(0, {ROOT!r})
+sys.path.insert(0, {root!r})
 import oracle as O
 from paper_1902_04661_amd import inputs as I
-it = I.ragged_batch(1, seed=0, fixed_n={N})[0]
+b = int(sys.argv[1])
+it = I.ragged_batch({batch}, seed=0, fixed_n={n})[b]
 m = O.model_from_item(it)
-opts = O.SolverOpts(tol={TOL}, restart=32)
+opts = O.SolverOpts(tol={tol}, restart=32)
 psi = it.psi0
 t0 = time.time(); steps = 0
 while True:
-    psi = O.propagate(m, psi, O.MIDP, O.SUZUKI, {ORDER}, {DT_STAR}, 1, opts)
+    psi = O.propagate(m, psi, O.MIDP, O.SUZUKI, {order}, {dt}, 1, opts)
     steps += 1
-    if time.time() - t0 > {seconds} or steps >= 400:
+    if time.time() - t0 > {seconds}:
         break
-el = time.time() - t0
-print(json.dumps(dict(steps=steps, seconds=el)))
+print(json.dumps(dict(steps=steps, seconds=time.time() - t0)))
 """
+
+
+def cpu_leg(seconds: float = 20.0, workers: int = 0) -> dict:
+    """The oracle on the host's cores: one process per core, each propagating one packet
+    of the benchmark's drawn batch (draw b on process b) by whole Suzuki-8 steps of dt*
+    at the same solve tolerance for about `seconds`.  value = sum over processes of
+    N x steps, over the wall time of the pool."""
+    cores = workers or min(16, os.cpu_count() or 1)
+    code = CPU_PACKET.format(root=ROOT, batch=BATCH, n=N, tol=TOL, order=ORDER, dt=DT_STAR, seconds=seconds)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
-    r = json.loads(out.stdout.strip().splitlines()[-1])
-    return {"value": N * r["steps"] / r["seconds"], "unit": "grid-point·steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"1 packet, N={N}, {r['steps']} SZ-8 steps of dt={DT_STAR} in {r['seconds']:.1f} s "
-                      f"(numpy FP64, one thread)"}
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen([sys.executable, "-c", code, str(b)], env=env, stdout=subprocess.PIPE, text=True)
+             for b in range(cores)]
+    outs = [json.loads(p.communicate()[0].strip().splitlines()[-1]) for p in procs]
+    wall = time.perf_counter() - t0
+    if any(p.returncode for p in procs):
+        raise RuntimeError("a CPU oracle process failed")
+    steps = sum(o["steps"] for o in outs)
+    return {"value": N * steps / wall, "unit": "grid-point·steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"draws 0..{cores - 1} of the benchmark batch, N={N}, one process (numpy FP64, one "
+                      f"thread) per packet, {steps} SZ-8 steps of dt={DT_STAR} in total (each process "
+                      f"{min(o['steps'] for o in outs)}-{max(o['steps'] for o in outs)} steps), "
+                      f"GMRES tol {TOL:g}, {wall:.1f} s wall"}
 
 
 def main(argv=None):
@@ -284,8 +345,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--single-steps", type=int, default=4)
+    ap.add_argument("--tj-steps", type=int, default=20, help="triple-jump leg (0: skip)")
     ap.add_argument("--ragged-batch", type=int, default=4096)
     ap.add_argument("--ragged-steps", type=int, default=2)
     ap.add_argument("--adjoint-batch", type=int, default=256)
@@ -296,6 +358,7 @@ def main(argv=None):
     ap.add_argument("--no-autotune", action="store_true", help="keep the default transform plans")
     ap.add_argument("--adjoint2d-steps", type=int, default=400)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device once (HBM counter calibration)")
@@ -323,37 +386,19 @@ def main(argv=None):
     opts = gqd.SolverOpts(tol=TOL, restart=32)
 
     # ---------------------------------------------------------------- batched run
-    items = [inputs.nai_like_item(N)] * args.batch
+    items = inputs.ragged_batch(args.batch, seed=0, fixed_n=N)
     prop = gqd.from_items(items, device=dev)
     psi0 = prop.pack([it.psi0 for it in items])
     psi = psi0.clone()
-    stream = torch.cuda.current_stream()
     plans = prop.autotune(psi, METHOD, SCHEME, 2, DT_STAR, 1, opts) if not args.no_autotune else {}
     print(f"[bench] transform plans: {plans}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         prop.propagate(psi, METHOD, SCHEME, ORDER, DT_STAR, 1, opts)
     print(f"[bench] warmup {args.warmup} steps done, batch {args.batch}", file=sys.stderr, flush=True)
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    bytes_total = 0.0
-    iters = iters_sq = solves = applies = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
-        st = prop.propagate(psi, METHOD, SCHEME, ORDER, DT_STAR, 1, opts)   # one launch
-        ends[k].record(stream)
-        bytes_total += alg_bytes(N, st)
-        iters += st.iterations
-        iters_sq += st.iterations_sq
-        solves += st.solves
-        applies += st.h_applies
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    avg_kernel_s = sum(kern_ms) / len(kern_ms) / 1e3
+    avg_kernel_s, wall, tot = timed_launches(prop, psi, args.steps, METHOD, SCHEME, ORDER, DT_STAR, opts)
     value = args.batch * N * args.steps / wall
-    achieved = bytes_total / args.steps / avg_kernel_s / 1e9
+    achieved = tot["bytes"] / args.steps / avg_kernel_s / 1e9
+    iters, solves = tot["iterations"], tot["solves"]
     print(f"[bench] timed {args.steps} steps: {wall:.2f} s wall, kernel {avg_kernel_s * 1e3:.1f} ms/step, "
           f"mean GMRES iterations {iters / solves:.2f}", file=sys.stderr, flush=True)
 
@@ -364,26 +409,32 @@ def main(argv=None):
         d1 = prop.diag(psi).cpu().numpy()
         check = {"max_norm_drift": float(np.max(np.abs(d1[:, 0] - d0[:, 0]))),
                  "max_energy_drift": float(np.max(np.abs(d1[:, 1] - d0[:, 1])))}
+    prop.close()
 
     # ------------------------------------------------------------- single packet
     single = {}
     if args.single_steps > 0:
-        it = inputs.nai_like_item(N)
-        p1 = gqd.from_items([it], device=dev)
-        s1 = p1.pack([it.psi0])
-        p1.propagate(s1, METHOD, SCHEME, ORDER, DT_STAR, 1, opts)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        st1 = p1.propagate(s1, METHOD, SCHEME, ORDER, DT_STAR, args.single_steps, opts)
-        torch.cuda.synchronize()
-        el1 = time.perf_counter() - t1
+        it = items[0]
+        with gqd.from_items([it], device=dev) as p1:
+            s1 = p1.pack([it.psi0])
+            p1.propagate(s1, METHOD, SCHEME, ORDER, DT_STAR, 1, opts)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st1 = p1.propagate(s1, METHOD, SCHEME, ORDER, DT_STAR, args.single_steps, opts)
+            torch.cuda.synchronize()
+            el1 = time.perf_counter() - t1
         single = {"value": N * args.single_steps / el1, "unit": "grid-point·steps/s",
                   "ms_per_step": 1e3 * el1 / args.single_steps,
                   "mean_gmres_iterations": st1.iterations / max(st1.solves, 1),
                   "us_per_h_apply": 1e6 * el1 / max(st1.h_applies, 1),
-                  "workload": f"one packet q0=5 p0=0 w=0.12, N={N}, SZ-8 midpoint, dt={DT_STAR}"}
+                  "workload": f"draw 0 of the batch alone, N={N}, SZ-8 midpoint, dt={DT_STAR}, GMRES tol {TOL:g}"}
         print(f"[bench] single packet: {single['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
 
+    tj = {}
+    if args.tj_steps > 0:
+        tj = triple_jump_leg(gqd, inputs, dev, items, args.tj_steps)
+        print(f"[bench] triple jump 8: {tj['value']:.3e} gp.steps/s, {tj['simulated_au_per_s']:.1f} a.u./s",
+              file=sys.stderr, flush=True)
     ragged = {}
     if args.ragged_batch > 0 and args.ragged_steps > 0:
         ragged = ragged_leg(gqd, inputs, dev, args.ragged_batch, args.ragged_steps)
@@ -415,10 +466,12 @@ def main(argv=None):
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_leg()
-        print(f"[bench] cpu oracle: {cpu['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
+        cpu = cpu_leg(args.cpu_seconds)
+        print(f"[bench] cpu oracle: {cpu['value']:.3e} gp.steps/s on {cpu['cores']} cores",
+              file=sys.stderr, flush=True)
 
-    traffic, traffic_ratio = measured_traffic() if args.batch == 1024 and not args.no_autotune else (None, None)
+    traffic, traffic_ratio = measured_traffic() if args.batch == BATCH and not args.no_autotune else (None, None)
+    sim = DT_STAR * args.steps / wall
     line = {
         "metric": METRIC,
         "value": value,
@@ -432,22 +485,25 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"nai2048_sz8_midpoint_dt10_x{args.batch}",
-                   "model": "two-surface NaI-like adiabatic model, N=2048 on [3,16) bohr; "
-                            "packet q0=5 p0=0 w=0.12 on surface 1, replicated",
+        "config": {"workload": f"nai2048_draws{args.batch}_sz8_midpoint_dt{DT_STAR:g}",
+                   "model": "two-surface NaI-like adiabatic model, N=2048 on [3,16) bohr; seeded draws "
+                            "q0~U[4.5,6], p0~U[-5,5], coupling amplitude~U[0.1,0.8], width 0.12 (seed 0)",
                    "batch": args.batch, "n": N, "method": "implicit midpoint", "scheme": "suzuki",
                    "order": ORDER, "dt": DT_STAR, "gmres_tol": TOL, "restart": 32,
                    "substeps_per_step": 125, "parallelism": "one workgroup per wavepacket",
+                   "dt_star_error": "<= 1e-10 at T=4000 a.u. for the batch's six highest-energy draws "
+                                    "(6.2e-11 worst; 1.4e-8 at dt=40)",
                    "transform_plan": list(plans.get(N, ())) or None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (launch from t = 0, rocprofv3 --pmc)",
                      "traffic_over_alg_bytes": traffic_ratio,
                      "kernel": "k_run<7> (propagate, N = 2048 plan 4-8-8-8)",
-                     "alg_bytes_per_launch": bytes_total / args.steps,
+                     "alg_bytes_per_launch": tot["bytes"] / args.steps,
                      "avg_launch_ms": avg_kernel_s * 1e3},
         "cpu_baseline": cpu,
         "single_packet": single,
+        "triple_jump_8": tj,
         "ragged_batch": ragged,
         "adjoint": adjoint,
         "two_dim": twod,
@@ -455,15 +511,17 @@ def main(argv=None):
         "elementary": elementary,
         "split_operator": split,
         # the batched and the differentiated forms against the plain one-packet solve, all
-        # at the same tolerance and step
+        # at the same tolerance and step; the two 8th-order schemes at their own 1e-10 steps
         "comparisons": {
             "batch_over_single_packet": value / single["value"] if single else None,
             "gradient_over_forward": adjoint.get("gradient_over_forward") if adjoint else None,
+            "simulated_au_per_s_suzuki8": sim,
+            "suzuki8_over_triple_jump8_at_1e-10": sim / tj["simulated_au_per_s"] if tj else None,
         },
-        "gmres": {"mean_iterations": iters / solves, "h_applies_per_step": applies / args.steps,
+        "gmres": {"mean_iterations": iters / solves, "h_applies_per_step": tot["h_applies"] / args.steps,
                   "solves_per_step": solves / args.steps,
                   "substeps_per_s": solves / (avg_kernel_s * args.steps),
-                  "h_applies_per_s": applies / (avg_kernel_s * args.steps)},
+                  "h_applies_per_s": tot["h_applies"] / (avg_kernel_s * args.steps)},
         "check": check,
     }
     print(json.dumps(line), flush=True)

@@ -193,6 +193,22 @@ gqd_status gqd_propagate(gqd_handle* h, gqd_method m, gqd_scheme s, int order, d
                          long long nsteps, void* psi, const gqd_solver_opts* o,
                          gqd_stats* st, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gqd_propagate on a 1D handle without
+ * the caller's workspace.  The solver works in a static device array that the library
+ * holds on every GPU it runs on until the process ends (64 MiB; its address is resolved
+ * in gqd_create), so the call needs no gqd_set_workspace and calls no hipMalloc, hipFree
+ * or other allocating routine, and creates no streams or events: the size classes run
+ * one after another on `stream`.  The batch must fit: (restart + 6) state vectors of
+ * 32 bytes per grid point (gqd_workspace_size) at most 64 MiB, else GQD_ERR_INVALID.
+ * Inputs, outputs, statistics and errors as gqd_propagate.  Every call on one GPU shares
+ * that GPU's array and leaves its contents behind (nothing in it is read before the call
+ * writes it), so calls that overlap in time on one GPU, on any streams or handles, race
+ * and must not be issued.  2D handles: GQD_ERR_UNSUPPORTED. */
+gqd_status gqd_propagate_noalloc(gqd_handle* h, gqd_method m, gqd_scheme s, int order, double dt,
+                                 long long nsteps, void* psi, const gqd_solver_opts* o,
+                                 gqd_stats* st, void* stream);
+
 /* As gqd_propagate, but item b takes its own step dt[b] and step count nsteps[b]
  * (DEVICE arrays of length batch; a negative dt propagates backward).  One launch
  * covers the whole batch, so items with different steps run side by side.  1D only. */

@@ -185,77 +185,201 @@ def _criterion(half: np.ndarray, kind: str) -> float:
     return float(np.max(np.abs(g))) if kind == "max" else float(np.sum(np.abs(g)))
 
 
-def newton(cond, x: np.ndarray, iters: int = 80, tol: float = 1e-15):
-    """Gauss-Newton onto cond(x) = 0 with minimum-norm steps (the system has fewer
-    conditions than unknowns) and step halving; returns (x, max |cond|)."""
+def newton(cond, x: np.ndarray, iters: int = 200, tol: float = 1e-15):
+    """Levenberg-Marquardt onto cond(x) = 0 with minimum-norm steps (the system has
+    fewer conditions than unknowns): dx = J^T (J J^T + mu 1)^-1 c, mu adapted to the
+    progress; returns (x, max |cond|)."""
     c = cond(x)
+    mu = 1e-3
     for _ in range(iters):
         err = float(np.max(np.abs(c)))
         if err <= tol:
             break
-        dx = np.linalg.lstsq(_jac(cond, x), c, rcond=None)[0]
-        t = 1.0
-        while t > 1e-4:
-            xn = x - t * dx
+        J = _jac(cond, x)
+        A = J @ J.T
+        while True:
+            y = np.linalg.solve(A + mu * np.eye(A.shape[0]), c)
+            xn = x - J.T @ y
             cn = cond(xn)
             if np.linalg.norm(cn) < np.linalg.norm(c):
+                x, c = xn, cn
+                mu = max(mu / 10.0, 1e-15)
                 break
-            t *= 0.5
-        if t <= 1e-4:
-            break
-        x, c = xn, cn
+            mu *= 10.0
+            if mu > 1e8:
+                return x, float(np.max(np.abs(c)))
     return x, float(np.max(np.abs(c)))
 
 
-def optimise(order: int, M: int, kind: str = "max", starts: int = 200, seed: int = 1,
-             scale: float = 0.6, log=None) -> Dict:
-    """Best palindromic composition of M substeps and the given order found from
-    `starts` seeded random starts: Gauss-Newton onto the solution set, then the
-    criterion (kind "max": max |g|; "sum": sum |g|) under the order conditions by
-    sequential quadratic programming, then Gauss-Newton again to full precision."""
+def _jac_batch(condb, X: np.ndarray) -> np.ndarray:
+    """Jacobians of a batched real-analytic condb at every row of X by complex steps:
+    (batch, conditions, unknowns)."""
+    B, n = X.shape
+    h = 1e-40
+    Z = (X.astype(np.complex128)[:, None, :] + 1j * h * np.eye(n)[None, :, :]).reshape(B * n, n)
+    return (condb(Z).imag / h).reshape(B, n, -1).transpose(0, 2, 1)
+
+
+def newton_batch(condb, X: np.ndarray, iters: int = 150, tol: float = 1e-15):
+    """Levenberg-Marquardt (minimum-norm damped steps, one damping per start) from every
+    row of X at once; returns (X, max |cond| per row)."""
+    X = X.copy()
+    C = condb(X)
+    mu = np.full(X.shape[0], 1e-3)
+    for _ in range(iters):
+        err = np.max(np.abs(C), axis=1)
+        live = (err > tol) & (mu < 1e8)
+        if not np.any(live):
+            break
+        Xl, Cl = X[live], C[live]
+        J = _jac_batch(condb, Xl)
+        A = J @ J.transpose(0, 2, 1) + mu[live][:, None, None] * np.eye(J.shape[1])[None]
+        y = np.linalg.solve(A, Cl[:, :, None])[:, :, 0]
+        Xn = Xl - np.einsum("bij,bi->bj", J, y)
+        Cn = condb(Xn)
+        better = np.linalg.norm(Cn, axis=1) < np.linalg.norm(Cl, axis=1)
+        idx = np.flatnonzero(live)
+        X[idx[better]] = Xn[better]
+        C[idx[better]] = Cn[better]
+        mu[idx[better]] = np.maximum(mu[idx[better]] / 10.0, 1e-15)
+        mu[idx[~better]] *= 10.0
+    return X, np.max(np.abs(C), axis=1)
+
+
+def homotopy(cond, x0: np.ndarray, tol: float = 1e-15, max_steps: int = 400):
+    """Newton homotopy onto cond(x) = 0: follow the solutions of cond(x) = (1 - t) cond(x0)
+    from t = 0 (x = x0) to t = 1 with adaptive steps in t, correcting each by
+    Levenberg-Marquardt; returns (x, max |cond|) (large when the path is lost)."""
+    c0 = cond(x0)
+    x, t, dt = x0.copy(), 0.0, 0.05
+    for _ in range(max_steps):
+        if t >= 1.0:
+            break
+        tn = min(1.0, t + dt)
+        target = (1.0 - tn) * c0
+        xn, err = newton(lambda z: cond(z) - target if np.ndim(z) == 1 else cond(z) - target[None, :],
+                         x, iters=12, tol=1e-13 if tn < 1.0 else tol)
+        if err <= (1e-10 if tn < 1.0 else 1e-13):
+            x, t = xn, tn
+            dt = min(2.0 * dt, 0.25)
+        else:
+            dt *= 0.5
+            if dt < 1e-6:
+                break
+    return newton(cond, x, iters=50, tol=tol)
+
+
+def refine(cond, x: np.ndarray, kind: str = "max", iters: int = 40):
+    """The criterion's optimum near x to full precision, from its optimality conditions.
+    kind "max" with two or more largest |g_n| within 1e-6 of each other: the square
+    system cond(x) = 0, |x_a| = |x_b|.  Otherwise (one largest |g_n| for "max", or
+    "sum" with no g_n at zero) the Lagrange conditions cond(x) = 0,
+    grad f(x) = J(x)^T lam, solved for (x, lam) by Newton with a difference Jacobian.
+    Returns x (unchanged when the iteration does not converge)."""
+    nh = x.size
+    w = np.array([2.0] * (nh - 1) + [1.0])  # multiplicity of each distinct coefficient
+    ax = np.abs(x)
+    order_ = np.argsort(-ax)
+    if kind == "max" and ax[order_[0]] - ax[order_[1]] < 1e-6:
+        a, b = order_[0], order_[1]
+        sa, sb = np.sign(x[a]), np.sign(x[b])
+        F = lambda z: np.concatenate([cond(z), [sa * z[a] - sb * z[b]]])  # noqa: E731
+        z = x.copy()
+        for _ in range(iters):
+            f = F(z)
+            if np.max(np.abs(f)) < 1e-16:
+                break
+            Jf = np.vstack([_jac(cond, z), (sa * np.eye(nh)[a] - sb * np.eye(nh)[b])[None]])
+            z = z - np.linalg.lstsq(Jf, f, rcond=None)[0]
+        return z if np.max(np.abs(cond(z))) < 1e-14 else x
+    if kind == "max":
+        a = order_[0]
+        grad = lambda z: np.sign(z[a]) * np.eye(nh)[a]  # noqa: E731
+    else:
+        grad = lambda z: w * np.sign(z)  # noqa: E731
+    J = _jac(cond, x)
+    lam = np.linalg.lstsq(J.T, grad(x), rcond=None)[0]
+    nc = lam.size
+
+    def F(v):
+        z, l = v[:nh], v[nh:]
+        return np.concatenate([cond(z), grad(x) - _jac(cond, z).T @ l])
+
+    v = np.concatenate([x, lam])
+    for _ in range(iters):
+        f = F(v)
+        if np.max(np.abs(f)) < 1e-15:
+            break
+        h = 1e-7
+        Jf = np.stack([(F(v + h * e) - F(v - h * e)) / (2 * h) for e in np.eye(v.size)], axis=1)
+        v = v - np.linalg.lstsq(Jf, f, rcond=None)[0]
+    z = v[:nh]
+    ok = np.max(np.abs(cond(z))) < 1e-14 and np.all(np.sign(z) == np.sign(x))
+    return z if ok else x
+
+
+def improve(order: int, x: np.ndarray, kind: str):
+    """From a point x on the solution set: the criterion's local optimum under the order
+    conditions (sequential quadratic programming, then Gauss-Newton back onto the
+    conditions and the optimality conditions to full precision), or None."""
     from scipy.optimize import minimize
 
-    nh = (M + 1) // 2
+    nh = x.size
     nc = condition_count(order)
-    rng = np.random.default_rng(seed)
-    def cond(x):
-        x = np.asarray(x)
-        return order_conditions(x, order) if x.ndim == 2 else order_conditions(x, order)[0]
 
+    def cond(z):
+        z = np.asarray(z)
+        return order_conditions(z, order) if z.ndim == 2 else order_conditions(z, order)[0]
+
+    if kind == "max":
+        z0 = np.concatenate([x, [_criterion(x, "max")]])
+        cons = [{"type": "eq", "fun": lambda z: cond(z[:-1]),
+                 "jac": lambda z: np.hstack([_jac(cond, z[:-1]), np.zeros((nc, 1))])},
+                {"type": "ineq", "fun": lambda z: np.concatenate([z[-1] - z[:-1], z[-1] + z[:-1]])}]
+        res = minimize(lambda z: z[-1], z0, jac=lambda z: np.eye(z.size)[-1], constraints=cons,
+                       method="SLSQP", options={"maxiter": 300, "ftol": 1e-15})
+        y = res.x[:-1]
+    else:
+        # sum |g| = 2 sum_{n < nh} |g_n| + |g_nh|, with g = u - v, u, v >= 0
+        w = np.array([2.0] * (nh - 1) + [1.0])
+        z0 = np.concatenate([np.maximum(x, 0), np.maximum(-x, 0)])
+        cons = [{"type": "eq", "fun": lambda z: cond(z[:nh] - z[nh:]),
+                 "jac": lambda z: np.hstack([_jac(cond, z[:nh] - z[nh:]), -_jac(cond, z[:nh] - z[nh:])])}]
+        res = minimize(lambda z: float(np.dot(w, z[:nh] + z[nh:])), z0,
+                       jac=lambda z: np.concatenate([w, w]), constraints=cons,
+                       bounds=[(0, None)] * (2 * nh), method="SLSQP", options={"maxiter": 500, "ftol": 1e-15})
+        y = res.x[:nh] - res.x[nh:]
+    y, err = newton(cond, y)
+    if err > 1e-14:
+        return None
+    return refine(cond, y, kind)
+
+
+def optimise(order: int, M: int, kind: str = "max", starts: int = 400, seed: int = 1,
+             scale: float = 0.8, seeds=(), log=None) -> Dict:
+    """Best palindromic composition of M substeps and the given order: Levenberg-Marquardt
+    from `starts` seeded random points (all at once) onto the solution set, plus any
+    given feasible `seeds`, then improve() from each; the best criterion value wins."""
+    nh = (M + 1) // 2
+    rng = np.random.default_rng(seed)
+    condb = lambda X: order_conditions(X, order)  # noqa: E731
+    X, err = newton_batch(condb, rng.uniform(-scale, scale, size=(starts, nh)))
+    cands = [x for x in X[err < 1e-12]] + [np.asarray(z, dtype=np.float64) for z in seeds]
+    if log:
+        log(f"order {order} M {M}: {len(cands)} feasible starting points")
     best = None
-    for s in range(starts):
-        x, err = newton(cond, rng.uniform(-scale, scale, size=nh))
-        if err > 1e-10:
+    for k, x in enumerate(cands):
+        y = improve(order, x, kind)
+        if y is None:
             continue
-        if kind == "max":
-            z0 = np.concatenate([x, [_criterion(x, "max")]])
-            cons = [{"type": "eq", "fun": lambda z: cond(z[:-1]),
-                     "jac": lambda z: np.hstack([_jac(cond, z[:-1]), np.zeros((nc, 1))])},
-                    {"type": "ineq", "fun": lambda z: np.concatenate([z[-1] - z[:-1], z[-1] + z[:-1]])}]
-            res = minimize(lambda z: z[-1], z0, jac=lambda z: np.eye(z.size)[-1], constraints=cons,
-                           method="SLSQP", options={"maxiter": 300, "ftol": 1e-15})
-            x = res.x[:-1]
-        else:
-            # sum |g| = 2 sum_{n < nh} |g_n| + |g_nh|, with g = u - v, u, v >= 0
-            w = np.array([2.0] * (nh - 1) + [1.0])
-            z0 = np.concatenate([np.maximum(x, 0), np.maximum(-x, 0)])
-            cons = [{"type": "eq", "fun": lambda z: cond(z[:nh] - z[nh:]),
-                     "jac": lambda z: np.hstack([_jac(cond, z[:nh] - z[nh:]), -_jac(cond, z[:nh] - z[nh:])])}]
-            res = minimize(lambda z: float(np.dot(w, z[:nh] + z[nh:])), z0,
-                           jac=lambda z: np.concatenate([w, w]), constraints=cons,
-                           bounds=[(0, None)] * (2 * nh), method="SLSQP",
-                           options={"maxiter": 500, "ftol": 1e-15})
-            x = res.x[:nh] - res.x[nh:]
-        x, err = newton(cond, x)
-        if err > 1e-14:
-            continue
-        c = _criterion(x, kind)
+        c = _criterion(y, kind)
         if best is None or c < best[0] - 1e-12:
-            best = (c, x)
+            best = (c, y)
             if log:
-                log(f"order {order} M {M}: start {s}: {kind} |g| = {c:.15f}")
+                log(f"order {order} M {M}: candidate {k}: {kind} |g| = {c:.15f}")
     if best is None:
         raise RuntimeError(f"no composition of order {order} with {M} substeps found")
     half = best[1]
     return {"order": order, "M": M, "criterion": kind, "value": best[0], "half": half.tolist(),
-            "gammas": palindrome(half).tolist(), "residual": float(np.max(np.abs(cond(half))))}
+            "gammas": palindrome(half).tolist(),
+            "residual": float(np.max(np.abs(order_conditions(half, order))))}

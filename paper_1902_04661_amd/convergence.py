@@ -76,11 +76,12 @@ def run_batch(item, scheme: str, order: int, dts: List[float], T: float, opts: g
 
 
 def step_errors(items, scheme: str, order: int, dt: float, T: float, opts: gqd.SolverOpts,
-                chunk: int = 64, log=print) -> List[float]:
+                chunk: int = 64, ref_dt: float | None = None, log=print) -> List[float]:
     """Convergence error of each item at time T for one step dt: the scheme's run against
-    the order-8 Suzuki run at dt / 8 (grid L2 norm)."""
+    the order-8 Suzuki run at ref_dt (default dt / 8), in the grid L2 norm."""
     runs = run_items(items, scheme, order, [dt] * len(items), T, opts, chunk, log)
-    refs = run_items(items, "suzuki", 8, [dt / 8.0] * len(items), T, opts, chunk, log)
+    rdt = dt / 8.0 if ref_dt is None else ref_dt
+    refs = run_items(items, "suzuki", 8, [rdt] * len(items), T, opts, chunk, log)
     return [grid_norm(it.dq, a - r) for it, a, r in zip(items, runs, refs)]
 
 
@@ -105,42 +106,62 @@ def sweep(item, T: float = 4000.0, dt0: float = 40.0, kmax: int = 3, order: int 
     return result
 
 
+def hardest_draws(draws: dict, count: int) -> np.ndarray:
+    """Indices of the `count` draws with the highest classical energy of the packet
+    centre, p0^2 / 2m + V_1(q0), highest first: the packets whose states carry the
+    largest energies, and with them the largest time-discretisation errors."""
+    E = draws["p0"] ** 2 / (2.0 * inputs.MASS) + inputs.morse(draws["q0"])
+    return np.argsort(-E, kind="stable")[:count]
+
+
 def packet_set(n: int = 2048, draws: int = 6, seed: int = 0, pool: int = 1024) -> List:
     """Packets for the step-size study at grid size n: the model's resting packet
     (q0 = 5, p0 = 0), a moving one (q0 = 5.05, p0 = 2.5; the second state of Sec. III's
-    symplectic-form test), and the `draws` fastest (largest |p0|) of `pool` seeded
-    ragged-batch draws on that grid (q0 ~ U[4.5, 6], p0 ~ U[-5, 5], coupling amplitude
-    ~ U[0.1, 0.8]): the fastest packets carry the largest kinetic energies and with them
-    the largest time-discretisation errors."""
+    symplectic-form test), and the `draws` highest-energy ones (hardest_draws) of the
+    `pool` seeded draws of the 8th-order batch (q0 ~ U[4.5, 6], p0 ~ U[-5, 5], coupling
+    amplitude ~ U[0.1, 0.8])."""
     d = inputs.ragged_batch_draws(pool, seed)
-    order = np.argsort(-np.abs(d["p0"]), kind="stable")[:draws]
     items = [inputs.nai_like_item(n), inputs.nai_like_item(n, q0=5.05, p0=2.5)]
-    for b in order:
+    for b in hardest_draws(d, draws):
         items.append(inputs.nai_like_item(n, q0=float(d["q0"][b]), p0=float(d["p0"][b]), amp=float(d["amp"][b])))
     return items
 
 
-def multi_sweep(items, T: float = 4000.0, dt0: float = 40.0, kmax: int = 3, tj_shift: int = 1,
-                tol: float = 1e-15, restart: int = 48, chunk: int = 200, log=print) -> dict:
-    """Order-8 Suzuki at dt_k = dt0 2^-k (k <= kmax) and order-8 triple jump at dt_(k+tj_shift),
-    each against the Suzuki-8 run at a step eight times smaller, for every packet; and the
-    floor of the references: the two finest Suzuki-8 runs against each other."""
+def multi_sweep(items, T: float = 4000.0, dt0: float = 80.0, sz_k=(0, 4), tj_k=(3, 8),
+                ref_min: float = 0.625, tol: float = 1e-17, restart: int = 48, chunk: int = 800,
+                dt_grid_max: float = 40.0, log=print) -> dict:
+    """Order-8 Suzuki at dt_k = dt0 2^-k for k in the range sz_k and order-8 triple jump
+    for k in tj_k, each against the order-8 Suzuki run at a step eight times smaller,
+    but never below ref_min (below it the finest Suzuki run serves: its own error is
+    orders below the tested ones, and a dt/8 rule there would take tens of millions
+    of solves); the floor of the references is the difference of the two finest
+    Suzuki runs.  dt_star of a scheme is the largest dt_k <= dt_grid_max whose error is
+    <= 1e-10 for every packet (the sweep's grid is 40 2^-k a.u.).
+    The default tol solves every system to stagnation: the residual estimate keeps
+    falling after the true residual has reached rounding level, so each solve then ends
+    a few iterations past it, and the tolerance-sized error that a stop at 1e-15 leaves
+    in every one of the references' million solves (it added up to 1e-9) is gone."""
     opts = gqd.SolverOpts(tol=tol, restart=restart, maxit=4000)
-    ks = kmax + tj_shift + 3  # the finest level: the last triple-jump run's reference
-    dts = [dt0 * 2.0 ** (-k) for k in range(ks + 1)]
+    dts_all = [dt0 * 2.0 ** (-k) for k in range(max(sz_k[1], tj_k[1]) + 4)]
+    ks = max(k for k, dt in enumerate(dts_all) if dt >= ref_min - 1e-12)
+    dts = dts_all[:ks + 1]
+    ref_of = lambda k: min(k + 3, ks)  # noqa: E731
     P = len(items)
     sz = run_items([it for it in items for _ in dts], "suzuki", 8, [dt for _ in items for dt in dts], T,
                    opts, chunk, log)
     sz = [sz[p * len(dts):(p + 1) * len(dts)] for p in range(P)]
-    tj_k = list(range(tj_shift, kmax + tj_shift + 1))
-    tj = run_items([it for it in items for _ in tj_k], "triple_jump", 8,
-                   [dts[k] for _ in items for k in tj_k], T, opts, chunk, log)
-    tj = [tj[p * len(tj_k):(p + 1) * len(tj_k)] for p in range(P)]
-    out = {"T": T, "tol": tol, "n": items[0].n, "dt_suzuki": dts[:kmax + 1], "dt_triple_jump": [dts[k] for k in tj_k],
-           "packets": []}
+    tjl = list(range(tj_k[0], tj_k[1] + 1))
+    szl = list(range(sz_k[0], sz_k[1] + 1))
+    tj = run_items([it for it in items for _ in tjl], "triple_jump", 8,
+                   [dts_all[k] for _ in items for k in tjl], T, opts, chunk, log)
+    tj = [tj[p * len(tjl):(p + 1) * len(tjl)] for p in range(P)]
+    out = {"T": T, "tol": tol, "n": items[0].n, "dt_suzuki": [dts[k] for k in szl],
+           "dt_triple_jump": [dts_all[k] for k in tjl],
+           "reference_dt_suzuki": [dts[ref_of(k)] for k in szl],
+           "reference_dt_triple_jump": [dts[ref_of(k)] for k in tjl], "packets": []}
     for p, it in enumerate(items):
-        e_sz = [grid_norm(it.dq, sz[p][k] - sz[p][k + 3]) for k in range(kmax + 1)]
-        e_tj = [grid_norm(it.dq, tj[p][i] - sz[p][k + 3]) for i, k in enumerate(tj_k)]
+        e_sz = [grid_norm(it.dq, sz[p][k] - sz[p][ref_of(k)]) for k in szl]
+        e_tj = [grid_norm(it.dq, tj[p][i] - sz[p][ref_of(k)]) for i, k in enumerate(tjl)]
         floor = grid_norm(it.dq, sz[p][ks - 1] - sz[p][ks])
         out["packets"].append({"q0": it.params["q0"], "p0": it.params["p0"], "amp": it.params["amp"],
                                "suzuki8": e_sz, "triple_jump8": e_tj, "reference_floor": floor,
@@ -149,7 +170,7 @@ def multi_sweep(items, T: float = 4000.0, dt0: float = 40.0, kmax: int = 3, tj_s
             f"TJ-8 {['%.1e' % e for e in e_tj]} floor {floor:.1e}")
     for key, dtl in (("suzuki8", out["dt_suzuki"]), ("triple_jump8", out["dt_triple_jump"])):
         worst = [max(pk[key][k] for pk in out["packets"]) for k in range(len(dtl))]
-        ok = [dtl[k] for k in range(len(dtl)) if worst[k] <= 1e-10]
+        ok = [dtl[k] for k in range(len(dtl)) if worst[k] <= 1e-10 and dtl[k] <= dt_grid_max]
         out.setdefault("worst", {})[key] = worst
         out.setdefault("dt_star", {})[key] = max(ok) if ok else None
     return out
@@ -159,7 +180,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--T", type=float, default=4000.0)
-    ap.add_argument("--dt0", type=float, default=40.0)
+    ap.add_argument("--dt0", type=float, default=40.0, help="largest step (packet-set sweep: 80)")
     ap.add_argument("--kmax", type=int, default=3)
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-14)
@@ -171,8 +192,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
     if args.draws >= 0:
-        res = multi_sweep(packet_set(args.n, args.draws), args.T, args.dt0, args.kmax, tol=args.tol,
-                          chunk=args.chunk, log=log)
+        res = multi_sweep(packet_set(args.n, args.draws), args.T, args.dt0, tol=args.tol, chunk=args.chunk,
+                          log=log)
     else:
         item = inputs.nai_like_item(args.n)
         res = sweep(item, args.T, args.dt0, args.kmax, args.order, tol=args.tol, chunk=args.chunk, log=log)

@@ -76,6 +76,7 @@ struct gqd_handle {
   size_t work_bytes = 0;
   int* solve_log = nullptr;  // optional per-solve iteration counts, log_cap per item
   long long log_cap = 0;
+  void* scratch = nullptr;   // this device's static scratch (gqd_propagate_noalloc)
   hipStream_t side[kNumClasses] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kNumClasses] = {};
@@ -463,6 +464,11 @@ gqd_status gqd_create(gqd_handle** out, const gqd_grid_desc* g) {
   if ((e = hipMalloc(&h->d_stats, sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc stats"));
   if ((e = hipMemset(h->d_stats, 0, sizeof(ItemStats) * g->batch)) != hipSuccess) return cleanup(hip_fail(e, "hipMemset stats"));
   if ((e = configure_kernels(kMaxRestart)) != hipSuccess) return cleanup(hip_fail(e, "configure kernels"));
+  {
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return cleanup(hip_fail(e, "hipGetDevice"));
+    if ((e = scratch_address(dev, &h->scratch)) != hipSuccess) return cleanup(hip_fail(e, "hipGetSymbolAddress scratch"));
+  }
   *out = h;
   return GQD_OK;
 }
@@ -684,6 +690,51 @@ gqd_status gqd_propagate(gqd_handle* h, gqd_method m, gqd_scheme sch, int order,
                          long long nsteps, void* psi, const gqd_solver_opts* o, gqd_stats* st,
                          void* stream) {
   return propagate_impl(h, m, sch, order, dt, nsteps, nullptr, nullptr, psi, o, st, stream);
+}
+
+gqd_status gqd_propagate_noalloc(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, double dt,
+                                 long long nsteps, void* psi, const gqd_solver_opts* o, gqd_stats* st,
+                                 void* stream) {
+  if (!h) return fail(GQD_ERR_INVALID, "handle is NULL");
+  if (h->dims != 1) return fail(GQD_ERR_UNSUPPORTED, "the allocation-free propagation runs 1D batches");
+  if (!h->V || !h->F) return fail(GQD_ERR_STATE, "surfaces not set (gqd_set_surfaces)");
+  gqd_status s = check_opts(h, o);
+  if (s != GQD_OK) return s;
+  if (!psi) return fail(GQD_ERR_INVALID, "NULL state pointer");
+  if (m != GQD_TRAP && m != GQD_MIDP && m != GQD_SPLIT_OPERATOR && !elementary(m))
+    return fail(GQD_ERR_INVALID, "unknown method");
+  if (elementary(m) && order != (m == GQD_SOD ? 2 : 1))
+    return fail(GQD_ERR_INVALID, "the Euler methods take order 1 and second-order differencing order 2");
+  if (!std::isfinite(dt)) return fail(GQD_ERR_INVALID, "dt must be finite");
+  if (nsteps < 0) return fail(GQD_ERR_INVALID, "nsteps must be >= 0");
+  const size_t need = work_need(h, o->restart);
+  if (need > kScratchBytes)
+    return fail(GQD_ERR_INVALID, "this batch needs " + std::to_string(need) + " bytes of workspace at restart " +
+                                     std::to_string(o->restart) + "; the static scratch holds " +
+                                     std::to_string(kScratchBytes));
+  if (!h->scratch) return fail(GQD_ERR_STATE, "no scratch address for this handle's device");
+  KArgs a = base_args(h);
+  s = elementary(m) ? make_gammas(GQD_SUZUKI, 2, &a.gt) : make_gammas(sch, order, &a.gt);
+  if (s != GQD_OK) return s;
+  a.psi = (double2*)psi;
+  a.work = (double2*)h->scratch;  // nothing in the scratch is read before it is written
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
+  a.mode = 0;
+  a.method = method_code(m);
+  a.dt = dt;
+  a.nsteps = nsteps;
+  a.hpsi_valid = 0;
+  // every size class on the caller's stream, one after another: no side streams or
+  // events are created
+  hipStream_t strm = (hipStream_t)stream;
+  for (int c = kNumClasses - 1; c >= 0; --c) {
+    if (h->class_lists[c].empty()) continue;
+    a.list = h->d_lists[c];
+    a.nlist = (int)h->class_lists[c].size();
+    a.tw = h->d_tw + h->tw_off[h->plan[c]];
+    GQD_HIP(m == GQD_SPLIT_OPERATOR ? launch_split(h->plan[c], a, strm) : launch_run(h->plan[c], a, strm));
+  }
+  return st ? collect_stats(h, strm, st) : GQD_OK;
 }
 
 gqd_status gqd_propagate_items(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, const double* dt,

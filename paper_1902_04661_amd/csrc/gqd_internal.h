@@ -263,6 +263,12 @@ inline size_t lds_bytes2(int n, int m) {
   return c * 16 + d * 8 + 64;
 }
 
+// The allocation-free entry point's workspace: a static device array of this size per
+// GPU (gqd_kernels.hip), its address resolved once per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_address(int device, void** ptr);
+
 // Kernel launchers (gqd_kernels.hip).  Each launches the items of a.list with one plan
 // (kPlans index) on `stream`.
 hipError_t launch_apply_h(int plan, const KArgs& a, hipStream_t stream);

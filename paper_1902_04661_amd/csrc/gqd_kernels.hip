@@ -8,6 +8,8 @@
 #include "gqd_internal.h"
 #include "gqd_compositions.h"
 
+#include <mutex>
+
 namespace gqd {
 
 
@@ -1585,6 +1587,32 @@ static hipError_t set_lds_limit(size_t bytes) {
   if ((e = hipFuncSetAttribute((const void*)k_diag<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_split<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_inner<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Workspace of the allocation-free entry point (gqd_propagate_noalloc): a file-scope
+// device array, one copy per GPU, held until the process ends.  Host code never uses
+// its name as an address (on the host it names a stand-in, not device memory): the
+// device address comes from hipGetSymbolAddress, once per device, with that device
+// current, and only that pointer is handed to kernels.
+static __device__ __align__(256) double2 scratch[kScratchBytes / sizeof(double2)];
+
+hipError_t scratch_address(int device, void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes it current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
 }
 
 hipError_t configure_kernels(int m_max) {

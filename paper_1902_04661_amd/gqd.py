@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "gqd_implicit_step": ([vp, i, d, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
         "gqd_propagate": ([vp, i, i, i, d, ll, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
         "gqd_propagate_items": ([vp, i, i, i, vp, vp, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
+        "gqd_propagate_noalloc": ([vp, i, i, i, d, ll, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
         "gqd_adjoint": ([vp, i, i, d, ll, vp, vp, vp, ctypes.POINTER(_SolverOpts), ctypes.POINTER(_Stats), vp], i),
         "gqd_autotune": ([vp, i, i, i, d, ll, vp, ctypes.POINTER(_SolverOpts), vp, vp], i),
         "gqd_list_plans": ([i, vp, i, ctypes.POINTER(i)], i),
@@ -112,7 +113,7 @@ def load_library(path: str = LIB_PATH):
 def exported_symbols() -> List[str]:
     return ["gqd_create", "gqd_destroy", "gqd_state_size", "gqd_state_offset",
             "gqd_workspace_size", "gqd_set_workspace", "gqd_set_surfaces", "gqd_apply_H",
-            "gqd_implicit_step", "gqd_propagate", "gqd_propagate_items", "gqd_adjoint", "gqd_autotune",
+            "gqd_implicit_step", "gqd_propagate", "gqd_propagate_items", "gqd_propagate_noalloc", "gqd_adjoint", "gqd_autotune",
             "gqd_list_plans", "gqd_set_plan", "gqd_set_wait_limit", "gqd_set_solve_log", "gqd_composition",
             "gqd_diag", "gqd_inner",
             "gqd_last_error"]
@@ -329,6 +330,19 @@ class Propagator:
         _check(_lib.gqd_propagate(self._h, _METHODS[method], _SCHEMES[scheme], int(order), float(dt),
                                   int(nsteps), self._state(psi), ctypes.byref(co),
                                   ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
+        return _stats(st)
+
+    def propagate_noalloc(self, psi: torch.Tensor, method="midp", scheme="suzuki", order: int = 2,
+                          dt: float = 1.0, nsteps: int = 1, opts: Optional[SolverOpts] = None,
+                          stats: bool = True, stream=None) -> Optional[Stats]:
+        """As propagate, in the library's static workspace: no device allocation (neither
+        here nor in the library); calls on one GPU must not overlap."""
+        opts = opts or SolverOpts()
+        co = opts.c()
+        st = _Stats() if stats else None
+        _check(_lib.gqd_propagate_noalloc(self._h, _METHODS[method], _SCHEMES[scheme], int(order), float(dt),
+                                          int(nsteps), self._state(psi), ctypes.byref(co),
+                                          ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
         return _stats(st)
 
     def propagate_items(self, psi: torch.Tensor, method="midp", scheme="suzuki", order: int = 2,
