@@ -39,8 +39,10 @@ def test_noalloc_matches_workspace_path_twice(sizes, seed):
 def test_noalloc_rejects_what_does_not_fit():
     from paper_1902_04661_amd import gqd
     gqd.load_library()
-    items = batch((4096,) * 8, 23)  # 8 x (64 + 6) x 2 x 4096 x 16 B > 64 MiB at restart 64
+    items = batch((4096,) * 16, 23)  # 16 x (32 + 6) x 2 x 4096 x 16 B = 80 MB > 64 MiB at restart 32
     with gqd.from_items(items) as prop:
         psi = prop.pack([it.psi0 for it in items])
         with pytest.raises(gqd.GqdError, match="static scratch"):
-            prop.propagate_noalloc(psi, "midp", "suzuki", 2, 10.0, 1, gqd.SolverOpts(restart=64))
+            prop.propagate_noalloc(psi, "midp", "suzuki", 2, 10.0, 1, gqd.SolverOpts(restart=32))
+        # the state is untouched by the rejected call
+        assert torch.equal(psi, prop.pack([it.psi0 for it in items]))
