@@ -11,9 +11,9 @@ conditions.
 
 Order conditions, in a matrix representation.  A symmetric second-order S has
 log S(h) = h Y1 + h^3 Y3 + h^5 Y5 + ... (odd powers only).  Take the Y_k to be seeded
-random real matrices (6 x 6: by the Amitsur-Levitzki theorem no nonzero polynomial of
-degree below 12 vanishes on all of them, so generic ones represent every condition up to
-degree 9 faithfully) and compute log U(h) as a power series in h with matrix
+random real d x d matrices with 2d > p - 1 (by the Amitsur-Levitzki theorem no nonzero
+polynomial of degree below 2d vanishes on all of them, so generic ones represent every
+condition up to degree p - 1 faithfully) and compute log U(h) as a power series in h with matrix
 coefficients, truncated above h^(p-1): U is of order p exactly when its h^1 coefficient
 is Y1 and its h^3, h^5, ... h^(p-1) coefficients vanish (even ones vanish by themselves
 for a palindromic g).  Those coefficients' entries form an overcomplete set of
@@ -40,14 +40,20 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HEADER = os.path.join(HERE, "csrc", "gqd_compositions.h")
-DIM = 6
+
+def dim_for(order: int) -> int:
+    """Smallest matrix size that represents the conditions of this order faithfully."""
+    return max(3, (order - 1) // 2 + 1)
+
 
 # order, substeps, criterion, random starts, seed of the starts
 SCHEMES = [(4, 5, "max", 200, 7), (6, 9, "max", 1000, 7), (8, 17, "max", 40000, 7), (10, 35, "sum", 40000, 7)]
 
 
-def generators(K: int, d: int = DIM, seed: int = 2019) -> np.ndarray:
-    """Y_1, Y_3, ..., Y_K as seeded random real d x d matrices, scaled to unit norm."""
+def generators(K: int, d: int = 0, seed: int = 2019) -> np.ndarray:
+    """Y_1, Y_3, ..., Y_K as seeded random real d x d matrices (d = dim_for(K + 1) by
+    default), scaled to unit norm."""
+    d = d or dim_for(K + 1)
     rng = np.random.default_rng(seed)
     Y = rng.standard_normal((len(range(1, K + 1, 2)), d, d))
     return Y / np.linalg.norm(Y, axis=(1, 2), keepdims=True)
@@ -139,37 +145,38 @@ def project(half: np.ndarray, order: int, Y: np.ndarray, iters: int = 60, rank: 
 
 
 def _feasible_batch(args) -> List[np.ndarray]:
-    """Levenberg-Marquardt from one batch of seeded uniform random points; the points
-    that reach the solution set."""
-    order, nh, seed, b, size, scale = args
+    """Levenberg-Marquardt from one batch of seeded uniform random points: damped
+    minimum-norm steps on the `ncond` leading singular directions of each Jacobian
+    (the conditions' rank); the points that reach the solution set."""
+    order, nh, seed, b, size, scale, ncond = args
     Y = generators(order - 1)
     X = np.random.default_rng([seed, b]).uniform(-scale, scale, size=(size, nh))
     R = residual(X, order, Y)
-    lam = np.full(X.shape[0], 1e-2)
-    for _ in range(100):
-        live = (np.max(np.abs(R), axis=1) > 1e-11) & (lam < 1e9)
+    lam = np.full(X.shape[0], 1e-3)
+    for _ in range(150):
+        live = (np.max(np.abs(R), axis=1) > 1e-11) & (lam < 1e8)
         if not live.any():
             break
-        J = jacobian(X[live], order, Y)
-        JT = np.swapaxes(J, -1, -2)
-        A = JT @ J + lam[live][:, None, None] * np.eye(nh)
-        step = np.linalg.solve(A, (JT @ R[live][..., None]))[..., 0]
-        Xn = X[live] - step
+        U, sv, Vt = np.linalg.svd(jacobian(X[live], order, Y), full_matrices=False)
+        U, sv, Vt = U[..., :ncond], sv[..., :ncond], Vt[..., :ncond, :]
+        coef = np.einsum("bek,be->bk", U, R[live]) * sv / (sv * sv + lam[live][:, None])
+        Xn = X[live] - np.einsum("bkn,bk->bn", Vt, coef)
         Rn = residual(Xn, order, Y)
         good = np.linalg.norm(Rn, axis=1) < np.linalg.norm(R[live], axis=1)
         idx = np.flatnonzero(live)
         X[idx[good]], R[idx[good]] = Xn[good], Rn[good]
-        lam[idx[good]] /= 5.0
-        lam[idx[~good]] *= 8.0
+        lam[idx[good]] = np.maximum(lam[idx[good]] / 10.0, 1e-15)
+        lam[idx[~good]] *= 10.0
     ok = np.max(np.abs(R), axis=1) <= 1e-11
     return list(X[ok])
 
 
-def feasible_points(order: int, nh: int, starts: int, seed: int, scale: float = 0.8, batch: int = 128,
-                    workers: int = 1, log=None) -> List[np.ndarray]:
+def feasible_points(order: int, nh: int, starts: int, seed: int, ncond: int, scale: float = 0.8,
+                    batch: int = 128, workers: int = 1, log=None) -> List[np.ndarray]:
     """Points on the solution set from `starts` seeded random points, in batches (batch b
     draws from default_rng([seed, b])), spread over `workers` processes."""
-    jobs = [(order, nh, seed, b, min(batch, starts - b * batch), scale) for b in range((starts + batch - 1) // batch)]
+    jobs = [(order, nh, seed, b, min(batch, starts - b * batch), scale, ncond)
+            for b in range((starts + batch - 1) // batch)]
     found: List[np.ndarray] = []
     if workers > 1:
         import multiprocessing as mp
@@ -276,7 +283,7 @@ def derive(order: int, M: int, kind: str, starts: int, seed: int, workers: int =
     s = np.linalg.svd(jacobian(np.random.default_rng(1).uniform(-0.5, 0.5, nh), order, Y), compute_uv=False)
     ncond = int(np.sum(s > 1e-8 * s[0]))
     best = None
-    for x in feasible_points(order, nh, starts, seed, workers=workers, log=log):
+    for x in feasible_points(order, nh, starts, seed, ncond, workers=workers, log=log):
         x = polish(descend(x, order, Y, kind, ncond), order, Y, kind, ncond)
         c = criterion(x, kind)
         if best is None or c < best[0] - 1e-13:

@@ -1186,26 +1186,42 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
       }
       case kSolveArnoldi: {
         // Arnoldi on H - s (the Krylov space of 1 + i al H is that of H - s for any real
-        // shift s): y = (H - s) v_j is orthogonalised against v_0..v_j by classical
-        // Gram-Schmidt, with a second pass only when the first cancels all but
-        // kReorthRatio of |w|^2.  With s near the Rayleigh quotient of v_0 that
-        // cancellation is small, and the second pass is rarely needed.
+        // shift s).  H - s is Hermitian, so w = (H - s) v_j lies, up to rounding, in the
+        // span of v_j, v_(j-1) and the new direction: those two are projected out first
+        // (their dot products in one reduction, the update from the stash that the same
+        // sweep filled), then one classical Gram-Schmidt pass over v_0..v_j, with |w1|^2
+        // from the same reduction, removes what rounding left along every basis vector.
+        // That pass cancels little; another runs only when it keeps less than
+        // kReorthRatio of |w1|^2.  (A full first pass would cancel more than half of
+        // |w|^2 on most iterations once the Lanczos coefficients settle, and need the
+        // second full pass every time.)
         // Column j of the Hessenberg matrix of X = 1 + i al H is delta_ij + i al (h_ij +
         // s delta_ij), and v_(j+1) = i sign(al) w'/|w'| makes its subdiagonal |al| |w'| real.
         ++iters;
         const double sh = opshift;
-        // |w'|^2 = |w|^2 - sum |h_i|^2 when the pass keeps at least half of |w|^2 (a
-        // few ulp there); a second pass returns its own |w'|^2 from the same reduction
+        const int k0 = j > 0 ? j - 1 : 0;
+        const int K0 = j - k0 + 1;
+        const cplx* b0 = basis + (size_t)k0 * E::VEC;
+        E::template block_dots<E::kStashFill>(b0, y, K0, c, c.y, false);
+        E::template block_axpy<true>(b0, c.y, K0, y, c);
+        // |w2|^2 = |w1|^2 - sum |c_i|^2 when the pass keeps at least half of |w1|^2 (a
+        // few ulp there); a further pass returns its own |w'|^2 from the same reduction
         E::template block_dots<E::kStashFill>(basis, y, j + 1, c, c.hcol, true);
         const double w2 = uniform_d(c.hcol[j + 1].x);
-        if (j == 0) {  // <v_0|H v_0>, the shift of the following columns and solves
-          const double rq = uniform_d(c.hcol[0].x) + sh;
-          if (kind_mu) sig1 = rq; else sig0 = rq;
-        }
         double hn2 = w2;
         for (int i = 0; i <= j; ++i) hn2 -= cabs2(c.hcol[i]);
         hn2 = uniform_d(hn2);
+        if (j == 0) {  // <v_0|H v_0>, the shift of the following columns and solves
+          // (read here: the column is rewritten below, behind barriers)
+          const double rq = uniform_d(c.hcol[0].x + c.y[0].x) + sh;
+          if (kind_mu) sig1 = rq; else sig0 = rq;
+        }
         E::template block_axpy<true>(basis, c.hcol, j + 1, y, c);
+        // every wave has read the pass's coefficients before the column gains the
+        // three-term ones, and the column is whole before anyone reads it below
+        __syncthreads();
+        if (threadIdx.x < K0) c.hcol[k0 + threadIdx.x] = cadd(c.hcol[k0 + threadIdx.x], c.y[threadIdx.x]);
+        __syncthreads();
         if (hn2 < kReorthRatio * w2) {
           E::template block_dots<E::kStashUse>(basis, y, j + 1, c, c.y, true);
           double r2 = uniform_d(c.y[j + 1].x);
@@ -1213,10 +1229,6 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           hn2 = uniform_d(r2 > 0.0 ? r2 : 0.0);
           E::template block_axpy<true>(basis, c.y, j + 1, y, c);
           for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);
-        } else {
-          // every wave has read h (above and in block_axpy) before the first wave
-          // overwrites it with the column of X below
-          __syncthreads();
         }
         const double hn = sqrt(hn2);
         for (int i = threadIdx.x; i <= j; i += T) {
