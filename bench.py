@@ -58,11 +58,11 @@ TOL_ADJ = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "4b6731f3a4c6e76581b18648d82b3e2c2f496015a576d22917c0f8ac8f4a595f",
-    "fetch_kib": 81256669.5, "fetch_scale": 2.0,
-    "write_kib": 56882301.625, "write_scale": 1.0,
-    "alg_bytes_same_launch": 330511155200.0,
-    "summary": "profiles/k_run_2048_sz8_x1024.md",
+    "sources_sha256": "61b9a078ccc135b2eac78be5e926f45f6232ca43c747418c1cf1355b1376f769",
+    "fetch_kib": 664521673.4375, "fetch_scale": 2.0,
+    "write_kib": 115155955.0, "write_scale": 1.0,
+    "alg_bytes_same_launch": 1518300495872.0,
+    "summary": "profiles/k_run_2048_sz8_draws1024.md",
 }
 DEVICE_SOURCES = ["gqd_kernels.hip", "gqd_device.hpp", "gqd_internal.h"]
 
@@ -216,13 +216,22 @@ def twod_leg(gqd, inputs, dev, steps: int) -> dict:
     with gqd.from_items([it], device=dev) as prop:
         psi = prop.pack([it.psi0])
         prop.propagate(psi, METHOD, SCHEME, ORDER, DT_2D, 1, opts)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        e0.record(s)
         st = prop.propagate(psi, METHOD, SCHEME, ORDER, DT_2D, steps, opts)
+        e1.record(s)
         el = time.perf_counter() - t0
+        kern = e0.elapsed_time(e1) * 1e-3
+    gbs = st.alg_bytes / kern / 1e9
     return {"value": 256 * 256 * steps / el, "unit": "grid-point·steps/s", "ms_per_step": 1e3 * el / steps,
             "mean_gmres_iterations": st.iterations / max(st.solves, 1),
-            "us_per_h_apply": 1e6 * el / max(st.h_applies, 1), "alg_GBps": st.alg_bytes / el / 1e9,
+            "us_per_h_apply": 1e6 * el / max(st.h_applies, 1),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "kernel": "k_run2d<256>", "launch_ms": kern * 1e3,
+                         "alg_bytes": st.alg_bytes},
             "workload": f"2D 256x256, Suzuki order 8 midpoint, dt={DT_2D}, {steps} steps, GMRES tol {TOL_2D:g}"}
 
 
@@ -291,8 +300,29 @@ def adjoint_leg(gqd, inputs, dev, batch: int, nsteps: int) -> dict:
         prop.propagate(psi, "midp", "suzuki", 4, 4.0, nsteps, opts, stats=False)
         torch.cuda.synchronize()
         fwd = time.perf_counter() - t1
+        # the reverse sweep alone from that psi(T), timed on its stream: its algorithmic
+        # bytes are those of its solves (two per substep) plus, per grid point and
+        # substep, reading phi, mu, psi and lambda, writing psi and lambda (6 state
+        # vectors of 32 B) and updating dL/dF12 (16 B)
+        lam = torch.zeros_like(psi)
+        lv = lam.view(batch, 2, 1024)
+        lv[:, 1] = items[0].dq * psi.view(batch, 2, 1024)[:, 1]
+        gF = torch.zeros(batch * 1024, dtype=torch.float64, device=dev)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        st = prop.adjoint(psi, lam, gF, "suzuki", 4, 4.0, nsteps, opts)
+        e1.record(s)
+        torch.cuda.synchronize()
+        rev = e0.elapsed_time(e1) * 1e-3
+    rev_bytes = st.alg_bytes + 208.0 * 1024 * batch * 5 * nsteps
     return {"value": batch / el, "unit": "gradients/s", "params_per_gradient": 5, "seconds": el,
             "forward_only_seconds": fwd, "gradient_over_forward": el / fwd,
+            "reverse_sweep": {"seconds": rev, "mean_gmres_iterations": st.iterations / max(st.solves, 1),
+                              "roofline": {"bound": "hbm", "achieved": rev_bytes / rev / 1e9, "peak": HBM_PEAK_GBS,
+                                           "unit": "GB/s", "frac": rev_bytes / rev / 1e9 / HBM_PEAK_GBS,
+                                           "kernel": "k_run<4> (reverse sweep, N = 1024)", "alg_bytes": rev_bytes}},
             "workload": f"{batch} packets, N=1024, Suzuki order 4, dt=4, {nsteps} steps, forward + reverse, "
                         f"GMRES tol {TOL_ADJ:g}"}
 
