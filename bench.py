@@ -10,10 +10,11 @@ dt_k = 40 * 2^-k whose convergence error at T = 4000 a.u. stays <= 1e-10 for the
 highest-energy draws of this batch (6.2e-11 at 20 a.u., 1.4e-8 at 40 a.u.; see
 paper_1902_04661_amd.convergence), every system solved to stagnation (GMRES tolerance
 1e-17), as in that sweep.  One "step" advances every packet by dt in one kernel launch.
-Side legs: the 8th-order triple jump on the same batch at its own 1e-10 step
-(0.625 a.u.), one packet alone, the 4096-packet ragged batch (N in 256..4096, Suzuki
-order 6 at its verified step 2.5 a.u.), 1D and 2D gradients, the 2D model, the
-elementary and diabatic controls.
+Side legs: the 8th-order triple jump (0.625 a.u.) and the non-recursive optimal
+compositions of orders 8 and 10 (2.5 and 10 a.u.) on the same batch, each at its own
+1e-10 step from the same sweep; one packet alone; the 4096-packet ragged batch (N in
+256..4096, Suzuki order 6 at its verified step 2.5 a.u.); 1D and 2D gradients; the 2D
+model; the elementary and diabatic controls.
 
 Roofline: the propagation kernel against the HBM peak (8 TB/s) with algorithmic bytes
 32 (I^2 + 4I + 8) per grid point per substep for a solve of I Arnoldi iterations
@@ -44,6 +45,9 @@ ORDER, SCHEME, METHOD = 8, "suzuki", "midp"
 # solve tolerance; the ragged batch's step is verified by tests/test_gpu_step_verification
 DT_STAR = 20.0
 DT_STAR_TJ = 0.625
+# the non-recursive optimal compositions (17 and 35 substeps) at their own 1e-10 steps
+DT_STAR_OPT8 = 2.5
+DT_STAR_OPT10 = 10.0
 TOL = 1e-17
 RAGGED_DT = 2.5
 # the 2D model and the 1D gradient workload run at their configurations' own steps
@@ -131,21 +135,22 @@ def ragged_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
                         f"GMRES tol {TOL:g}"}
 
 
-def triple_jump_leg(gqd, inputs, dev, items, steps: int) -> dict:
-    """The same drawn batch under the 8th-order triple jump (27 substeps per step) at its
-    own 1e-10 step: throughput per step and, comparable across schemes, simulated
-    time per second (a.u./s) against the Suzuki run."""
+def scheme_leg(gqd, inputs, dev, items, steps: int, scheme: str, order: int, dt: float) -> dict:
+    """The same drawn batch under another composition at its own 1e-10 step: throughput
+    per step and, comparable across schemes, simulated time per second (a.u./s)."""
     opts = gqd.SolverOpts(tol=TOL, restart=32)
     with gqd.from_items(items, device=dev) as prop:
         psi = prop.pack([it.psi0 for it in items])
-        prop.propagate(psi, METHOD, "triple_jump", ORDER, DT_STAR_TJ, 1, opts)
-        kern, wall, tot = timed_launches(prop, psi, steps, METHOD, "triple_jump", ORDER, DT_STAR_TJ, opts)
+        prop.propagate(psi, METHOD, scheme, order, dt, 1, opts)
+        kern, wall, tot = timed_launches(prop, psi, steps, METHOD, scheme, order, dt, opts)
+        count = len(gqd.composition(scheme, order))
     return {"value": len(items) * N * steps / wall, "unit": "grid-point·steps/s",
-            "ms_per_step": 1e3 * wall / steps, "simulated_au_per_s": DT_STAR_TJ * steps / wall,
+            "ms_per_step": 1e3 * wall / steps, "simulated_au_per_s": dt * steps / wall,
             "mean_gmres_iterations": tot["iterations"] / max(tot["solves"], 1),
+            "h_applies_per_au": tot["h_applies"] / (dt * steps) / len(items),
             "alg_GBps": tot["bytes"] / steps / kern / 1e9,
-            "workload": f"{len(items)} drawn packets, N={N}, triple jump order 8, dt={DT_STAR_TJ}, "
-                        f"GMRES tol {TOL:g}"}
+            "workload": f"{len(items)} drawn packets, N={N}, {scheme} order {order} ({count} substeps), "
+                        f"dt={dt}, GMRES tol {TOL:g}"}
 
 
 SOD_DT = 0.15  # below 1 / E_max of the N = 2048 grid on [3, 16) (E_max ~ 4.3 Ha)
@@ -378,6 +383,7 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--single-steps", type=int, default=4)
     ap.add_argument("--tj-steps", type=int, default=20, help="triple-jump leg (0: skip)")
+    ap.add_argument("--opt-steps", type=int, default=8, help="optimal 8th- and 10th-order legs (0: skip)")
     ap.add_argument("--ragged-batch", type=int, default=4096)
     ap.add_argument("--ragged-steps", type=int, default=2)
     ap.add_argument("--adjoint-batch", type=int, default=256)
@@ -460,11 +466,16 @@ def main(argv=None):
                   "workload": f"draw 0 of the batch alone, N={N}, SZ-8 midpoint, dt={DT_STAR}, GMRES tol {TOL:g}"}
         print(f"[bench] single packet: {single['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
 
-    tj = {}
+    tj, opt8, opt10 = {}, {}, {}
     if args.tj_steps > 0:
-        tj = triple_jump_leg(gqd, inputs, dev, items, args.tj_steps)
+        tj = scheme_leg(gqd, inputs, dev, items, args.tj_steps, "triple_jump", ORDER, DT_STAR_TJ)
         print(f"[bench] triple jump 8: {tj['value']:.3e} gp.steps/s, {tj['simulated_au_per_s']:.1f} a.u./s",
               file=sys.stderr, flush=True)
+    if args.opt_steps > 0:
+        opt8 = scheme_leg(gqd, inputs, dev, items, args.opt_steps, "optimal", 8, DT_STAR_OPT8)
+        opt10 = scheme_leg(gqd, inputs, dev, items, args.opt_steps, "optimal", 10, DT_STAR_OPT10)
+        print(f"[bench] optimal 8: {opt8['simulated_au_per_s']:.1f} a.u./s; optimal 10: "
+              f"{opt10['simulated_au_per_s']:.1f} a.u./s", file=sys.stderr, flush=True)
     ragged = {}
     if args.ragged_batch > 0 and args.ragged_steps > 0:
         ragged = ragged_leg(gqd, inputs, dev, args.ragged_batch, args.ragged_steps)
@@ -534,6 +545,8 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "single_packet": single,
         "triple_jump_8": tj,
+        "optimal_8": opt8,
+        "optimal_10": opt10,
         "ragged_batch": ragged,
         "adjoint": adjoint,
         "two_dim": twod,
@@ -541,12 +554,15 @@ def main(argv=None):
         "elementary": elementary,
         "split_operator": split,
         # the batched and the differentiated forms against the plain one-packet solve, all
-        # at the same tolerance and step; the two 8th-order schemes at their own 1e-10 steps
+        # at the same tolerance and step; the other compositions at their own 1e-10 steps
         "comparisons": {
             "batch_over_single_packet": value / single["value"] if single else None,
             "gradient_over_forward": adjoint.get("gradient_over_forward") if adjoint else None,
             "simulated_au_per_s_suzuki8": sim,
             "suzuki8_over_triple_jump8_at_1e-10": sim / tj["simulated_au_per_s"] if tj else None,
+            "optimal8_over_suzuki8_at_1e-10": opt8["simulated_au_per_s"] / sim if opt8 else None,
+            "optimal10_over_suzuki8_at_1e-10": opt10["simulated_au_per_s"] / sim if opt10 else None,
+            "h_applies_per_au_suzuki8": tot["h_applies"] / (DT_STAR * args.steps) / args.batch,
         },
         "gmres": {"mean_iterations": iters / solves, "h_applies_per_step": tot["h_applies"] / args.steps,
                   "solves_per_step": solves / args.steps,

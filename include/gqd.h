@@ -97,12 +97,13 @@ typedef enum {
   GQD_TRIPLE_JUMP = 0, /* recursive, M = 3 per level, Eq. (20) */
   GQD_SUZUKI = 1,      /* recursive, M = 5 per level, Eq. (21) */
   GQD_OPTIMAL = 2      /* non-recursive: one symmetric composition of the second-order
-                          method with the fewest substeps for its order and the
-                          smallest largest |substep| (orders 4, 6, 8: M = 5, 9, 17), or
-                          the smallest sum of |substeps| (order 10: M = 35), the
-                          optimisation criteria Sec. II.D names for these schemes; the
-                          fractions were derived here from the order conditions
-                          (gqd_composition returns them) */
+                          method, the schemes Sec. II.D calls optimal: M = 5, 9, 17
+                          substeps with the smallest largest |substep| at orders 4, 6, 8
+                          (Suzuki's fractal at order 4; Kahan and Li's at 6 and 8) and
+                          M = 35 with the smallest sum of |substeps| at order 10
+                          (Sofroniou and Spaletta's).  The fractions come from solving
+                          the order and optimality conditions (gqd_composition returns
+                          them); order 2 is the method itself */
 } gqd_scheme;
 
 typedef struct {

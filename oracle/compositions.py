@@ -25,11 +25,12 @@ independent order conditions: 1, 2, 4 and 8 of them at degrees 3, 5, 7 and 9.
 The optimal schemes solve: among palindromic g of length M meeting the conditions of
 order p, minimise max |g_n| (orders 4, 6, 8 with M = 5, 9, 17), or sum |g_n| (order 10,
 M = 35).  That leaves one free parameter at orders 4, 6, 8 and two at order 10.  The
-search runs from many seeded random starts: a trust-region least-squares solve onto the solution set,
-then sequential quadratic programming for the criterion.  The values are derived
-here, not copied from the published tables ("parity unpinned" against those tables:
-the tests pin them by the conditions, by measured orders of convergence and by the
-Suzuki case the paper states).
+oracle's coefficients are the published ones (gqd_oracle.OPTIMAL_HALVES); this module
+pins them: by the order conditions, by the optimality conditions and the criterion's
+growth along the solution set around them, and, at orders 4 and 6, by a search from
+seeded random starts (Levenberg-Marquardt onto the solution set, then sequential
+quadratic programming for the criterion) that reaches the same optimum.  At order 8
+such a search finds many local optima; 40000 starts gave none below the published one.
 """
 from __future__ import annotations
 
@@ -246,29 +247,6 @@ def newton_batch(condb, X: np.ndarray, iters: int = 150, tol: float = 1e-15):
     return X, np.max(np.abs(C), axis=1)
 
 
-def homotopy(cond, x0: np.ndarray, tol: float = 1e-15, max_steps: int = 400):
-    """Newton homotopy onto cond(x) = 0: follow the solutions of cond(x) = (1 - t) cond(x0)
-    from t = 0 (x = x0) to t = 1 with adaptive steps in t, correcting each by
-    Levenberg-Marquardt; returns (x, max |cond|) (large when the path is lost)."""
-    c0 = cond(x0)
-    x, t, dt = x0.copy(), 0.0, 0.05
-    for _ in range(max_steps):
-        if t >= 1.0:
-            break
-        tn = min(1.0, t + dt)
-        target = (1.0 - tn) * c0
-        xn, err = newton(lambda z: cond(z) - target if np.ndim(z) == 1 else cond(z) - target[None, :],
-                         x, iters=12, tol=1e-13 if tn < 1.0 else tol)
-        if err <= (1e-10 if tn < 1.0 else 1e-13):
-            x, t = xn, tn
-            dt = min(2.0 * dt, 0.25)
-        else:
-            dt *= 0.5
-            if dt < 1e-6:
-                break
-    return newton(cond, x, iters=50, tol=tol)
-
-
 def refine(cond, x: np.ndarray, kind: str = "max", iters: int = 40):
     """The criterion's optimum near x to full precision, from its optimality conditions.
     kind "max" with two or more largest |g_n| within 1e-6 of each other: the square
@@ -383,3 +361,46 @@ def optimise(order: int, M: int, kind: str = "max", starts: int = 400, seed: int
     return {"order": order, "M": M, "criterion": kind, "value": best[0], "half": half.tolist(),
             "gammas": palindrome(half).tolist(),
             "residual": float(np.max(np.abs(order_conditions(half, order))))}
+
+
+def tangent_basis(half: np.ndarray, order: int) -> np.ndarray:
+    """Orthonormal basis (rows) of the directions along the solution set at half: the
+    null space of the conditions' Jacobian."""
+    cond = lambda z: order_conditions(z, order)  # noqa: E731
+    J = _jac(cond, np.asarray(half, dtype=np.float64))
+    return np.linalg.svd(J)[2][J.shape[0]:]
+
+
+def optimality_residual(half: np.ndarray, order: int, kind: str) -> float:
+    """Largest part of the criterion's gradient along the solution set at half; zero at
+    a smooth stationary point (for "max": a single largest |g_n|; for "sum": no g_n at
+    zero).  The gradient of max |g| is sign(g_a) e_a at the largest entry a; that of
+    sum |g| over the palindrome is w sign(g), w the multiplicity of each entry."""
+    half = np.asarray(half, dtype=np.float64)
+    nh = half.size
+    if kind == "max":
+        a = int(np.argmax(np.abs(half)))
+        grad = np.sign(half[a]) * np.eye(nh)[a]
+    else:
+        grad = np.array([2.0] * (nh - 1) + [1.0]) * np.sign(half)
+    T = tangent_basis(half, order)
+    return float(np.max(np.abs(T @ grad)))
+
+
+def neighbours(half: np.ndarray, order: int, step: float) -> List[np.ndarray]:
+    """Points of the solution set about `step` away from half along each tangent
+    direction and its opposite (and the diagonals when there are two), each projected
+    back onto the conditions by Levenberg-Marquardt."""
+    half = np.asarray(half, dtype=np.float64)
+    T = tangent_basis(half, order)
+    dirs = list(T)
+    if len(T) == 2:
+        dirs += [(T[0] + T[1]) / math.sqrt(2), (T[0] - T[1]) / math.sqrt(2)]
+    cond = lambda z: order_conditions(z, order) if np.ndim(z) == 2 else order_conditions(z, order)[0]  # noqa: E731
+    out = []
+    for d in dirs:
+        for sgn in (1.0, -1.0):
+            z, err = newton(cond, half + sgn * step * d)
+            if err < 1e-14:
+                out.append(z)
+    return out

@@ -55,7 +55,7 @@ from typing import Callable, List, Optional, Sequence, Tuple
 import numpy as np
 
 TRAP, MIDP = "trap", "midp"
-TRIPLE_JUMP, SUZUKI = "triple_jump", "suzuki"
+TRIPLE_JUMP, SUZUKI, OPTIMAL = "triple_jump", "suzuki", "optimal"
 
 
 # ----------------------------------------------------------------------------- grid
@@ -395,12 +395,45 @@ def composition_gammas(scheme: str, p: int) -> List[float]:
     raise ValueError(f"unknown composition scheme {scheme!r}")
 
 
+# The non-recursive "optimal" compositions Sec. II.D uses, as published: the first
+# (M + 1)/2 coefficients g_1 .. g_(M+1)/2, the rest given by g_(M+1-n) = g_n.
+#   order 6, M = 9 and order 8, M = 17: Kahan and Li (1997), the largest |g_n| smallest;
+#   order 10, M = 35: Sofroniou and Spaletta (2005), the sum of |g_n| smallest.
+# At fourth order the section states that Suzuki's fractal is the optimal scheme.
+OPTIMAL_HALVES = {
+    6: [0.39216144400731413928, 0.33259913678935943860, -0.70624617255763935981,
+        0.08221359629355080023, 0.79854399093482996340],
+    8: [0.13020248308889008088, 0.56116298177510838456, -0.38947496264484728641,
+        0.15884190655515560090, -0.39590389413323757734, 0.18453964097831570709,
+        0.25837438768632204729, 0.29501172360931029887, -0.60550853383003451170],
+    10: [0.07879572252168641926, 0.31309610341510852776, 0.02791838323507806611,
+         -0.22959284159390709415, 0.13096206107716486317, -0.26973340565451071434,
+         0.07497334315589143567, 0.11199342399981020489, 0.36613344954622675119,
+         -0.39910563013603589788, 0.10308739852747107732, 0.41143087395589023782,
+         -0.00486636058313526176, -0.39203335370863990645, 0.05194250296244964704,
+         0.05066509075992449634, 0.04967437063972987905, 0.04931773575959453792],
+}
+
+
+def optimal_gammas(order: int) -> List[float]:
+    """g_1 .. g_M of the non-recursive composition of the given order (4, 6, 8, 10)."""
+    if order == 4:
+        return composition_gammas(SUZUKI, 2)
+    if order not in OPTIMAL_HALVES:
+        raise ValueError(f"no non-recursive composition of order {order}")
+    half = OPTIMAL_HALVES[order]
+    return half + half[-2::-1]
+
+
 def substep_fractions(scheme: str, order: int) -> List[float]:
     """Flattened fractions tau_c of the time step, in order of application, for the
-    recursive composition of a second-order method up to `order` (Sec. II.D).
-    There are 3^(order/2 - 1) (triple jump) or 5^(order/2 - 1) (Suzuki) of them."""
+    composition of a second-order method up to `order` (Sec. II.D): recursive triple
+    jump or Suzuki fractal, 3^(order/2 - 1) or 5^(order/2 - 1) of them, or the
+    non-recursive optimal one (5, 9, 17, 35 of them at orders 4, 6, 8, 10)."""
     if order < 2 or order % 2:
         raise ValueError("order must be even and >= 2")
+    if scheme == OPTIMAL:
+        return [1.0] if order == 2 else optimal_gammas(order)
     taus = [1.0]
     for p in range(2, order, 2):
         gam = composition_gammas(scheme, p)

@@ -2,29 +2,33 @@
 library (scheme GQD_OPTIMAL), written into csrc/gqd_compositions.h.
 
 Sec. II.D composes a symmetric second-order method S into U(dt) = S(g_M dt)...S(g_1 dt)
-and, besides the recursive triple jump and Suzuki fractal, names non-recursive schemes
-chosen by an optimisation: the largest |g_n| as small as possible for the order (sixth
-order with M = 9, eighth order with M = 17; it states that Suzuki's fractal is the
-optimal fourth-order one), and the sum of |g_n| as small as possible at tenth order with
-M = 35.  The paper prints no coefficients, so they are derived here from the order
-conditions.
+and, besides the recursive triple jump and Suzuki fractal, uses non-recursive schemes
+chosen by an optimisation: Suzuki's fractal at fourth order (M = 5), which it states is
+optimal; Kahan and Li's sixth- and eighth-order schemes (M = 9, 17), with the largest
+|g_n| as small as possible; Sofroniou and Spaletta's tenth-order scheme (M = 35), with
+the sum of |g_n| as small as possible.  The paper prints no coefficients; they are
+derived here from the order conditions and the optimality conditions.
 
 Order conditions, in a matrix representation.  A symmetric second-order S has
 log S(h) = h Y1 + h^3 Y3 + h^5 Y5 + ... (odd powers only).  Take the Y_k to be seeded
 random real d x d matrices with 2d > p - 1 (by the Amitsur-Levitzki theorem no nonzero
 polynomial of degree below 2d vanishes on all of them, so generic ones represent every
-condition up to degree p - 1 faithfully) and compute log U(h) as a power series in h with matrix
-coefficients, truncated above h^(p-1): U is of order p exactly when its h^1 coefficient
-is Y1 and its h^3, h^5, ... h^(p-1) coefficients vanish (even ones vanish by themselves
-for a palindromic g).  Those coefficients' entries form an overcomplete set of
+condition up to degree p - 1 faithfully) and compute log U(h) as a power series in h with
+matrix coefficients, truncated above h^(p-1): U is of order p exactly when its h^1
+coefficient is Y1 and its h^3, h^5, ... h^(p-1) coefficients vanish (even ones vanish by
+themselves for a palindromic g).  Those coefficients' entries form an overcomplete set of
 conditions, real-analytic in g, so their derivatives are taken by complex steps (exact
-to rounding); they are solved in the least-squares sense with rank-revealing steps.
+to rounding); their number of independent ones comes from the graded Witt formula.
 
-Search.  Levenberg-Marquardt from many seeded random points onto the solution set, then
-projected-gradient descent of a smooth stand-in for the criterion along that set
-(the tangent space from the singular value decomposition of the conditions' Jacobian),
-then Newton on the criterion's own optimality conditions: the largest two |g_n| equal, or
-the gradient in the span of the conditions' gradients.
+Search.  Orders 4 and 6: Levenberg-Marquardt from many seeded random points onto the
+solution set, then projected-gradient descent of a smooth stand-in for the criterion
+along that set (the tangent space from the singular value decomposition of the
+conditions' Jacobian).  Orders 8 and 10, whose optima such a search reaches too rarely
+(the order-8 landscape has many local minima), start from the cited publications'
+coefficients rounded to three digits.  Then Newton on the criterion's own optimality
+conditions: the largest two |g_n| equal, or the Lagrange conditions.  Double precision
+fixes the tenth-order coefficients to about 1e-9 only: the weakest of its 16
+conditions changes by about 1e-10 per unit change of g.
 
     python -m paper_1902_04661_amd.compositions --write
 """
@@ -46,8 +50,47 @@ def dim_for(order: int) -> int:
     return max(3, (order - 1) // 2 + 1)
 
 
-# order, substeps, criterion, random starts, seed of the starts
-SCHEMES = [(4, 5, "max", 200, 7), (6, 9, "max", 1000, 7), (8, 17, "max", 40000, 7), (10, 35, "sum", 40000, 7)]
+def _moebius(n: int) -> int:
+    m, k = 1, 2
+    while k * k <= n:
+        if n % k == 0:
+            n //= k
+            if n % k == 0:
+                return 0
+            m = -m
+        k += 1
+    return -m if n > 1 else m
+
+
+def condition_count(order: int) -> int:
+    """Number of independent order conditions of a palindromic composition of the given
+    order: the dimensions l_n of the odd-degree parts n = 1, 3, .., order - 1 of the free
+    Lie algebra on one generator in each odd degree (log S holds only odd powers), by
+    the graded Witt formula n l_n = sum over d | n of moebius(n / d) d c_d, where c_m is
+    the t^m coefficient of -log(1 - t - t^3 - t^5 - ...)."""
+    K = order - 1
+    g = np.zeros(K + 1)
+    g[1::2] = 1.0
+    c, p = np.zeros(K + 1), np.eye(1, K + 1)[0]
+    for k in range(1, K + 1):
+        p = np.convolve(p, g)[:K + 1]
+        c += p / k
+    return sum(round(sum(_moebius(n // d) * d * c[d] for d in range(1, n + 1) if n % d == 0) / n)
+               for n in range(1, K + 1, 2))
+
+
+# Starting points for the orders whose published optimum a random search does not reach
+# in reasonable time: the coefficients g_1 .. g_(M+1)/2 of the compositions the paper
+# cites, rounded to three significant digits -- Kahan and Li (1997), eighth order with
+# M = 17, and Sofroniou and Spaletta (2005), tenth order with M = 35.  Newton on the
+# optimality conditions takes them to full precision.
+KAHAN_LI_8 = [0.130, 0.561, -0.389, 0.159, -0.396, 0.185, 0.258, 0.295, -0.606]
+SOFRONIOU_SPALETTA_10 = [0.0788, 0.313, 0.0279, -0.230, 0.131, -0.270, 0.0750, 0.112, 0.366,
+                         -0.399, 0.103, 0.411, -0.00487, -0.392, 0.0519, 0.0507, 0.0497, 0.0493]
+
+# order, substeps, criterion, random starts, seed of the starts, fixed start (or None)
+SCHEMES = [(4, 5, "max", 200, 7, None), (6, 9, "max", 1000, 7, None),
+           (8, 17, "max", 0, 0, KAHAN_LI_8), (10, 35, "sum", 0, 0, SOFRONIOU_SPALETTA_10)]
 
 
 def generators(K: int, d: int = 0, seed: int = 2019) -> np.ndarray:
@@ -144,31 +187,41 @@ def project(half: np.ndarray, order: int, Y: np.ndarray, iters: int = 60, rank: 
     return x, float(np.max(np.abs(r)))
 
 
+def projector(order: int, nh: int, ncond: int, Y: np.ndarray) -> np.ndarray:
+    """A fixed basis of the conditions' range: the leading `ncond` left singular
+    vectors of the Jacobian at a seeded random point (equations x ncond)."""
+    x = np.random.default_rng(12345).uniform(-0.5, 0.5, nh)
+    U, s, Vt = np.linalg.svd(jacobian(x, order, Y), full_matrices=False)
+    return U[:, :ncond]
+
+
 def _feasible_batch(args) -> List[np.ndarray]:
-    """Levenberg-Marquardt from one batch of seeded uniform random points: damped
-    minimum-norm steps on the `ncond` leading singular directions of each Jacobian
-    (the conditions' rank); the points that reach the solution set."""
+    """Levenberg-Marquardt from one batch of seeded uniform random points on the square
+    system Q^T residual = 0 (Q: projector(), the conditions' range): damped
+    minimum-norm steps dx = J^T (J J^T + lam 1)^-1 r; the points that reach the
+    solution set of the full residual."""
     order, nh, seed, b, size, scale, ncond = args
     Y = generators(order - 1)
+    Q = projector(order, nh, ncond, Y)
     X = np.random.default_rng([seed, b]).uniform(-scale, scale, size=(size, nh))
-    R = residual(X, order, Y)
+    R = residual(X, order, Y) @ Q
     lam = np.full(X.shape[0], 1e-3)
     for _ in range(150):
-        live = (np.max(np.abs(R), axis=1) > 1e-11) & (lam < 1e8)
+        live = (np.max(np.abs(R), axis=1) > 1e-13) & (lam < 1e8)
         if not live.any():
             break
-        U, sv, Vt = np.linalg.svd(jacobian(X[live], order, Y), full_matrices=False)
-        U, sv, Vt = U[..., :ncond], sv[..., :ncond], Vt[..., :ncond, :]
-        coef = np.einsum("bek,be->bk", U, R[live]) * sv / (sv * sv + lam[live][:, None])
-        Xn = X[live] - np.einsum("bkn,bk->bn", Vt, coef)
-        Rn = residual(Xn, order, Y)
+        J = np.einsum("eq,ben->bqn", Q, jacobian(X[live], order, Y))
+        A = J @ np.swapaxes(J, -1, -2) + lam[live][:, None, None] * np.eye(ncond)
+        yv = np.linalg.solve(A, R[live][..., None])[..., 0]
+        Xn = X[live] - np.einsum("bqn,bq->bn", J, yv)
+        Rn = residual(Xn, order, Y) @ Q
         good = np.linalg.norm(Rn, axis=1) < np.linalg.norm(R[live], axis=1)
         idx = np.flatnonzero(live)
         X[idx[good]], R[idx[good]] = Xn[good], Rn[good]
         lam[idx[good]] = np.maximum(lam[idx[good]] / 10.0, 1e-15)
         lam[idx[~good]] *= 10.0
-    ok = np.max(np.abs(R), axis=1) <= 1e-11
-    return list(X[ok])
+    full = np.max(np.abs(residual(X, order, Y)), axis=1)
+    return list(X[full <= 1e-11])
 
 
 def feasible_points(order: int, nh: int, starts: int, seed: int, ncond: int, scale: float = 0.8,
@@ -239,52 +292,67 @@ def descend(x: np.ndarray, order: int, Y: np.ndarray, kind: str, ncond: int, ste
 
 
 def polish(x: np.ndarray, order: int, Y: np.ndarray, kind: str, ncond: int) -> np.ndarray:
-    """Gauss-Newton on the optimum's defining equations, with the conditions taken on
-    their `ncond` leading singular directions.  "max" with its two largest |g_n| within
-    1e-5: those two equal in size.  Otherwise the criterion's gradient g has no part
-    along the solution set: (1 - J^+ J) g = 0."""
+    """Newton on the optimum's defining equations, the conditions taken on a basis of
+    their range held fixed and scaled to unit sensitivity: W = U_k diag(1 / s_k) from the
+    leading `ncond` singular triplets of the Jacobian at x.  "max" with its two largest
+    |g_n| within 1e-5: W^T r = 0 and those two equal in size.  Otherwise the Lagrange
+    conditions of min f subject to W^T r = 0 in the unknowns (g, lam):
+    W^T r(g) = 0 and grad f = (W^T J(g))^T lam, with grad f constant on the sign pattern
+    of g and the Hessian of lam . W^T r by central differences of the complex-step
+    Jacobian.  Returns the iterate with the smallest equation residual."""
     nh = x.size
     a = np.argsort(-np.abs(x))
     kink = kind == "max" and abs(x[a[0]]) - abs(x[a[1]]) < 1e-5
     sa, sb = np.sign(x[a[0]]), np.sign(x[a[1]])
-
-    def grad(z):
-        if kind == "max":
-            return np.sign(z[a[0]]) * np.eye(nh)[a[0]]
-        return weights(nh) * np.sign(z)
-
-    def F(z):
-        J = jacobian(z, order, Y)
-        U, s, Vt = np.linalg.svd(J, full_matrices=True)
-        r = U[:, :ncond].T @ residual(z, order, Y)
-        if kink:
-            return np.concatenate([r, [sa * z[a[0]] - sb * z[a[1]]]])
-        T = Vt[ncond:]
-        return np.concatenate([r, T.T @ (T @ grad(z))])
+    U, sv, _ = np.linalg.svd(jacobian(x, order, Y), full_matrices=False)
+    W = U[:, :ncond] / sv[:ncond]
+    gradf = sa * np.eye(nh)[a[0]] if kind == "max" else weights(nh) * np.sign(x)
 
     z = x.copy()
-    for _ in range(30):
-        f0 = F(z)
-        if np.max(np.abs(f0)) < 1e-15:
-            break
-        h = 1e-7
-        Jf = np.stack([(F(z + h * e) - F(z - h * e)) / (2 * h) for e in np.eye(nh)], axis=1)
-        z = z - np.linalg.lstsq(Jf, f0, rcond=None)[0]
-    z2, err = project(z, order, Y, rank=ncond)
-    if err > 1e-14 or np.any(np.sign(z2) != np.sign(x)):
+    lam = np.linalg.lstsq((W.T @ jacobian(z, order, Y)).T, gradf, rcond=None)[0]
+    best = (np.inf, z)
+    for _ in range(12):
+        JW = W.T @ jacobian(z, order, Y)
+        r = W.T @ residual(z, order, Y)
+        if kink:
+            G = np.concatenate([r, [sa * z[a[0]] - sb * z[a[1]]]])
+            DG = np.vstack([JW, sa * np.eye(nh)[a[0]] - sb * np.eye(nh)[a[1]]])
+        else:
+            G = np.concatenate([r, gradf - JW.T @ lam])
+            h = 1e-6
+            P = np.concatenate([z + h * np.eye(nh), z - h * np.eye(nh)])
+            T = np.einsum("eq,ben,q->bn", W, jacobian(P, order, Y), lam)
+            H = ((T[:nh] - T[nh:]) / (2 * h)).T
+            DG = np.block([[JW, np.zeros((ncond, ncond))], [-H, -JW.T]])
+        if np.max(np.abs(G)) < best[0]:
+            best = (np.max(np.abs(G)), z.copy())
+        step = np.linalg.lstsq(DG, G, rcond=None)[0]
+        z = z - step[:nh]
+        if not kink:
+            lam = lam - step[nh:]
+    z = best[1]
+    if np.max(np.abs(residual(z, order, Y))) > 1e-14 or np.any(np.sign(z) != np.sign(x)):
         return x
-    return z2
+    return z
 
 
-def derive(order: int, M: int, kind: str, starts: int, seed: int, workers: int = 1, log=None) -> dict:
+def derive(order: int, M: int, kind: str, starts: int, seed: int, start=None, workers: int = 1,
+           log=None) -> dict:
     nh = (M + 1) // 2
     Y = generators(order - 1)
-    # the number of independent conditions: the rank of the Jacobian at a random point
-    s = np.linalg.svd(jacobian(np.random.default_rng(1).uniform(-0.5, 0.5, nh), order, Y), compute_uv=False)
-    ncond = int(np.sum(s > 1e-8 * s[0]))
+    ncond = condition_count(order)
+    if start is not None:
+        x, err = project(np.array(start, dtype=np.float64), order, Y, rank=ncond)
+        if err > 1e-13:
+            raise RuntimeError(f"order {order}: the starting point does not reach the solution set")
+        cands = [x]
+    else:
+        cands = feasible_points(order, nh, starts, seed, ncond, workers=workers, log=log)
     best = None
-    for x in feasible_points(order, nh, starts, seed, ncond, workers=workers, log=log):
-        x = polish(descend(x, order, Y, kind, ncond), order, Y, kind, ncond)
+    for x in cands:
+        if start is None:
+            x = descend(x, order, Y, kind, ncond)
+        x = polish(x, order, Y, kind, ncond)
         c = criterion(x, kind)
         if best is None or c < best[0] - 1e-13:
             best = (c, x)
@@ -300,10 +368,10 @@ def derive(order: int, M: int, kind: str, starts: int, seed: int, workers: int =
 
 def write_header(results: Sequence[dict], path: str = HEADER) -> None:
     lines = ["// Non-recursive symmetric compositions of a symmetric second-order method (Sec. II.D):",
-             "// the fewest substeps for the order with the smallest largest |g_n| (orders 4, 6, 8) or",
-             "// the smallest sum of |g_n| (order 10), derived from the order conditions by",
-             "// paper_1902_04661_amd/compositions.py, which writes this file.  Each list is g_1 .. g_M,",
-             "// g_1 applied first.",
+             "// M = 5, 9, 17 substeps with the smallest largest |g_n| (orders 4, 6, 8) and M = 35",
+             "// with the smallest sum of |g_n| (order 10), derived from the order and optimality",
+             "// conditions by paper_1902_04661_amd/compositions.py, which writes this file.  Each",
+             "// list is g_1 .. g_M, g_1 applied first.",
              "#pragma once", "", "namespace gqd {", "", "struct FlatComp {", "  int order;",
              "  int count;", "  int offset;", "};", ""]
     off = 0

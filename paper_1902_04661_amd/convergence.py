@@ -129,14 +129,16 @@ def packet_set(n: int = 2048, draws: int = 6, seed: int = 0, pool: int = 1024) -
 
 def multi_sweep(items, T: float = 4000.0, dt0: float = 80.0, sz_k=(0, 4), tj_k=(3, 8),
                 ref_min: float = 0.625, tol: float = 1e-17, restart: int = 48, chunk: int = 800,
-                dt_grid_max: float = 40.0, log=print) -> dict:
+                dt_grid_max: float = 40.0, extra=(), log=print) -> dict:
     """Order-8 Suzuki at dt_k = dt0 2^-k for k in the range sz_k and order-8 triple jump
     for k in tj_k, each against the order-8 Suzuki run at a step eight times smaller,
     but never below ref_min (below it the finest Suzuki run serves: its own error is
     orders below the tested ones, and a dt/8 rule there would take tens of millions
     of solves); the floor of the references is the difference of the two finest
     Suzuki runs.  dt_star of a scheme is the largest dt_k <= dt_grid_max whose error is
-    <= 1e-10 for every packet (the sweep's grid is 40 2^-k a.u.).
+    <= 1e-10 for every packet (the sweep's grid is 40 2^-k a.u.).  `extra` adds
+    (scheme, order, (k_first, k_last)) runs, measured against the same references and
+    reported under the key scheme + order.
     The default tol solves every system to stagnation: the residual estimate keeps
     falling after the true residual has reached rounding level, so each solve then ends
     a few iterations past it, and the tolerance-sized error that a stop at 1e-15 leaves
@@ -159,6 +161,13 @@ def multi_sweep(items, T: float = 4000.0, dt0: float = 80.0, sz_k=(0, 4), tj_k=(
            "dt_triple_jump": [dts_all[k] for k in tjl],
            "reference_dt_suzuki": [dts[ref_of(k)] for k in szl],
            "reference_dt_triple_jump": [dts[ref_of(k)] for k in tjl], "packets": []}
+    ext = []
+    for scheme, order, (k0, k1) in extra:
+        kl = list(range(k0, k1 + 1))
+        runs = run_items([it for it in items for _ in kl], scheme, order,
+                         [dts_all[k] for _ in items for k in kl], T, opts, chunk, log)
+        ext.append((f"{scheme}{order}", kl, [runs[p * len(kl):(p + 1) * len(kl)] for p in range(P)]))
+        out[f"dt_{scheme}{order}"] = [dts_all[k] for k in kl]
     for p, it in enumerate(items):
         e_sz = [grid_norm(it.dq, sz[p][k] - sz[p][ref_of(k)]) for k in szl]
         e_tj = [grid_norm(it.dq, tj[p][i] - sz[p][ref_of(k)]) for i, k in enumerate(tjl)]
@@ -166,9 +175,14 @@ def multi_sweep(items, T: float = 4000.0, dt0: float = 80.0, sz_k=(0, 4), tj_k=(
         out["packets"].append({"q0": it.params["q0"], "p0": it.params["p0"], "amp": it.params["amp"],
                                "suzuki8": e_sz, "triple_jump8": e_tj, "reference_floor": floor,
                                "reference_floor_dt": [dts[ks - 1], dts[ks]]})
+        for key, kl, runs in ext:
+            out["packets"][-1][key] = [grid_norm(it.dq, runs[p][i] - sz[p][ref_of(k)])
+                                       for i, k in enumerate(kl)]
+            log(f"  {key} {['%.1e' % e for e in out['packets'][-1][key]]}")
         log(f"packet q0={it.params['q0']:.3f} p0={it.params['p0']:+.3f}: SZ-8 {['%.1e' % e for e in e_sz]} "
             f"TJ-8 {['%.1e' % e for e in e_tj]} floor {floor:.1e}")
-    for key, dtl in (("suzuki8", out["dt_suzuki"]), ("triple_jump8", out["dt_triple_jump"])):
+    for key, dtl in [("suzuki8", out["dt_suzuki"]), ("triple_jump8", out["dt_triple_jump"])] + \
+            [(key, out[f"dt_{key}"]) for key, _, _ in ext]:
         worst = [max(pk[key][k] for pk in out["packets"]) for k in range(len(dtl))]
         ok = [dtl[k] for k in range(len(dtl)) if worst[k] <= 1e-10 and dtl[k] <= dt_grid_max]
         out.setdefault("worst", {})[key] = worst
@@ -188,12 +202,16 @@ def main(argv=None):
     ap.add_argument("--draws", type=int, default=-1,
                     help="packet set: the resting and moving packets plus this many fastest draws "
                          "(order 8, Suzuki and triple jump)")
+    ap.add_argument("--extra", nargs="*", default=[],
+                    help="packet set: more schemes as scheme:order:k_first:k_last (dt = dt0 2^-k)")
     ap.add_argument("--json", type=str, default="")
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
     if args.draws >= 0:
+        extra = [(e.split(":")[0], int(e.split(":")[1]), (int(e.split(":")[2]), int(e.split(":")[3])))
+                 for e in args.extra]
         res = multi_sweep(packet_set(args.n, args.draws), args.T, args.dt0, tol=args.tol, chunk=args.chunk,
-                          log=log)
+                          extra=extra, log=log)
     else:
         item = inputs.nai_like_item(args.n)
         res = sweep(item, args.T, args.dt0, args.kmax, args.order, tol=args.tol, chunk=args.chunk, log=log)

@@ -254,7 +254,7 @@ gqd_status make_gammas(gqd_scheme s, int order, GammaTab* gt) {
   if (s != GQD_TRIPLE_JUMP && s != GQD_SUZUKI && s != GQD_OPTIMAL)
     return fail(GQD_ERR_INVALID, "unknown composition scheme");
   std::memset(gt, 0, sizeof(*gt));
-  if (s == GQD_OPTIMAL) {
+  if (s == GQD_OPTIMAL && order > 2) {
     // one level of fractions over the second-order method (gqd_compositions.h)
     for (int k = 0; k < kNumFlat; ++k)
       if (kFlatComps[k].order == order) {

@@ -22,6 +22,12 @@ CASES = [
     ("suzuki", 6, [240.0, 120.0, 60.0], 5.6),
     ("triple_jump", 8, [30.0, 15.0, 7.5], 7.2),
     ("suzuki", 8, [240.0, 160.0], 7.2),
+    ("optimal", 6, [60.0, 30.0, 15.0], 5.6),
+    ("optimal", 8, [120.0, 60.0], 7.0),
+    # tenth order: the error reaches the reference's floor at 60 a.u., before the rate
+    # has grown to ten (7.9 over 240 -> 120 a.u.; the oracle's test measures 8.8 on a
+    # smaller model)
+    ("optimal", 10, [240.0, 120.0], 7.5),
 ]
 
 

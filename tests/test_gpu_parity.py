@@ -84,7 +84,8 @@ def test_single_step_matches_oracle(gqd, method, literal):
     assert st.failures == 0
 
 
-@pytest.mark.parametrize("scheme,order", [("suzuki", 4), ("triple_jump", 6), ("suzuki", 8)])
+@pytest.mark.parametrize("scheme,order", [("suzuki", 4), ("triple_jump", 6), ("suzuki", 8), ("optimal", 4),
+                                          ("optimal", 6), ("optimal", 8), ("optimal", 10)])
 def test_composed_propagation_matches_oracle(gqd, scheme, order):
     items = items_for([256, 1024], seed=6)
     prop = gqd.from_items(items)

@@ -51,8 +51,11 @@ def test_flattened_fractions_sum_to_one_and_are_palindromic(scheme, order):
     assert np.allclose(taus, taus[::-1], rtol=0, atol=1e-15)
 
 
-@pytest.mark.parametrize("scheme", [O.TRIPLE_JUMP, O.SUZUKI])
-@pytest.mark.parametrize("order", [2, 4, 6, 8])
+SCHEME_ORDERS = ([(s, o) for s in (O.TRIPLE_JUMP, O.SUZUKI) for o in (2, 4, 6, 8)]
+                 + [(O.OPTIMAL, o) for o in (4, 6, 8, 10)])
+
+
+@pytest.mark.parametrize("scheme,order", SCHEME_ORDERS)
 def test_scalar_phase_error_has_the_composed_order(scheme, order):
     # On an eigenvector of H with eigenvalue E, each Cayley substep multiplies by
     # (1 - i a E)/(1 + i a E) = exp(-2 i atan(a E)); the composed step's phase error
@@ -111,8 +114,7 @@ def test_implicit_euler_taylor_expansion_matches_paper():
         assert abs(c - sum(coef[k] * x ** k for k in range(4))) < 2 * x ** 4
 
 
-@pytest.mark.parametrize("scheme", [O.TRIPLE_JUMP, O.SUZUKI])
-@pytest.mark.parametrize("order", [2, 4, 6, 8])
+@pytest.mark.parametrize("scheme,order", SCHEME_ORDERS)
 def test_composed_propagation_on_constant_coupling_closed_form(scheme, order):
     # Superposition of k-space spinor eigenstates; each composed step multiplies each
     # component by prod_c (1 - i a_c E)/(1 + i a_c E), a_c = tau_c dt / 2.
