@@ -190,6 +190,107 @@ def multi_sweep(items, T: float = 4000.0, dt0: float = 80.0, sz_k=(0, 4), tj_k=(
     return out
 
 
+# Fig. 6 analogue: the trapezoidal rule and its compositions, each over steps that
+# bracket the errors 1e-5 and (where reachable in minutes) 1e-10 at T = 4000 a.u. for
+# the highest-energy draw of the 8th-order batch
+EFFICIENCY_CASES = [
+    ("suzuki", 2, [2.5, 1.25, 0.625, 0.3125, 0.15625, 0.078125]),
+    ("triple_jump", 4, [1.25, 0.625, 0.3125, 0.15625]),
+    ("suzuki", 4, [5.0, 2.5, 1.25, 0.625, 0.3125]),
+    ("triple_jump", 6, [2.5, 1.25, 0.625, 0.3125, 0.15625]),
+    ("suzuki", 6, [20.0, 10.0, 5.0, 2.5, 1.25]),
+    ("optimal", 6, [10.0, 5.0, 2.5, 1.25, 0.625]),
+    ("triple_jump", 8, [5.0, 2.5, 1.25, 0.625]),
+    ("suzuki", 8, [80.0, 40.0, 20.0, 10.0]),
+    ("optimal", 8, [20.0, 10.0, 5.0, 2.5]),
+    ("optimal", 10, [40.0, 20.0, 10.0, 5.0]),
+]
+
+
+def timed_run(item, method: str, scheme: str, order: int, dt: float, T: float, opts: gqd.SolverOpts,
+              chunk: int = 2048):
+    """One packet alone to time T: (final state, GPU seconds summed over the launches with
+    HIP events on the launch stream, summed statistics)."""
+    nsteps = int(round(T / dt))
+    if abs(nsteps * dt - T) > 1e-9 * T:
+        raise ValueError(f"T = {T} is not a whole number of steps of {dt}")
+    tot = dict(solves=0, iterations=0, h_applies=0)
+    secs = 0.0
+    with gqd.from_items([item]) as prop:
+        psi = prop.pack([item.psi0])
+        stream = torch.cuda.current_stream()
+        done = 0
+        while done < nsteps:
+            k = min(chunk, nsteps - done)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            st = prop.propagate(psi, method, scheme, order, dt, k, opts)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            secs += e0.elapsed_time(e1) * 1e-3
+            for key in tot:
+                tot[key] += getattr(st, key)
+            done += k
+        out = prop.unpack(psi)[0]
+    return out, secs, tot
+
+
+def cost_at(errors: Sequence[float], costs: Sequence[float], target: float, order: int):
+    """Cost to reach `target` error: log-log interpolation between the two runs that
+    bracket it; below the finest run, extrapolation along the asymptotic line
+    error ~ dt^order, cost ~ 1 / dt from the finest run.  (cost, extrapolated) or
+    (None, False) when even the coarsest run is below the target (cost unresolved)."""
+    for k in range(len(errors) - 1):
+        e0, e1 = errors[k], errors[k + 1]
+        if e0 >= target >= e1:
+            w = math.log(e0 / target) / math.log(e0 / e1)
+            return math.exp((1 - w) * math.log(costs[k]) + w * math.log(costs[k + 1])), False
+    if errors[-1] > target:
+        return costs[-1] * (errors[-1] / target) ** (1.0 / order), True
+    return None, False
+
+
+def efficiency(item, T: float = 4000.0, cases=EFFICIENCY_CASES, method: str = "trap",
+               ref=("optimal", 10, 1.25), tol: float = 1e-17, restart: int = 48, log=print) -> dict:
+    """Convergence error against GPU time per scheme (Sec. III, Fig. 6): every run is one
+    packet alone, its error the grid L2 distance at T to the reference run (by default
+    the optimal tenth-order composition at 1.25 a.u., as the paper takes its finest
+    optimal tenth-order run), its cost the GPU time of its launches and its count of H
+    applications.  Costs at errors 1e-5 and 1e-10 by cost_at()."""
+    opts = gqd.SolverOpts(tol=tol, restart=restart, maxit=4000)
+    t0 = time.time()
+    ref_state, ref_s, _ = timed_run(item, method, ref[0], ref[1], ref[2], T, opts)
+    log(f"  reference {ref[0]}-{ref[1]} dt {ref[2]}: {ref_s:.1f} s GPU")
+    out = {"T": T, "n": item.n, "method": method, "tol": tol, "reference": list(ref),
+           "packet": dict(item.params), "cases": []}
+    for scheme, order, dts in cases:
+        rec = {"scheme": scheme, "order": order, "dt": list(dts), "error": [], "gpu_s": [], "h_applies": [],
+               "solves": [], "iterations": []}
+        for dt in dts:
+            psi, secs, tot = timed_run(item, method, scheme, order, dt, T, opts)
+            rec["error"].append(grid_norm(item.dq, psi - ref_state))
+            rec["gpu_s"].append(secs)
+            rec["h_applies"].append(tot["h_applies"])
+            rec["solves"].append(tot["solves"])
+            rec["iterations"].append(tot["iterations"])
+            log(f"  {scheme}-{order} dt {dt:g}: error {rec['error'][-1]:.2e}, {secs:.2f} s GPU, "
+                f"{tot['h_applies']} H applications ({time.time() - t0:.0f} s)")
+        for target in (1e-5, 1e-10):
+            c, x = cost_at(rec["error"], rec["gpu_s"], target, order)
+            h, _ = cost_at(rec["error"], rec["h_applies"], target, order)
+            rec[f"gpu_s_at_{target:g}"] = c
+            rec[f"h_applies_at_{target:g}"] = h
+            rec[f"extrapolated_at_{target:g}"] = x
+        out["cases"].append(rec)
+    base = out["cases"][0]
+    for rec in out["cases"]:
+        for target in (1e-5, 1e-10):
+            k = f"gpu_s_at_{target:g}"
+            rec[f"speedup_over_{base['scheme']}{base['order']}_at_{target:g}"] = (
+                base[k] / rec[k] if base.get(k) and rec.get(k) else None)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--n", type=int, default=2048)
@@ -204,10 +305,18 @@ def main(argv=None):
                          "(order 8, Suzuki and triple jump)")
     ap.add_argument("--extra", nargs="*", default=[],
                     help="packet set: more schemes as scheme:order:k_first:k_last (dt = dt0 2^-k)")
+    ap.add_argument("--efficiency", action="store_true",
+                    help="error against GPU time of the trapezoidal rule and its compositions "
+                         "for the batch's highest-energy draw")
     ap.add_argument("--json", type=str, default="")
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
-    if args.draws >= 0:
+    if args.efficiency:
+        d = inputs.ragged_batch_draws(1024, 0)
+        b = int(hardest_draws(d, 1)[0])
+        item = inputs.nai_like_item(args.n, q0=float(d["q0"][b]), p0=float(d["p0"][b]), amp=float(d["amp"][b]))
+        res = efficiency(item, args.T, tol=args.tol, log=log)
+    elif args.draws >= 0:
         extra = [(e.split(":")[0], int(e.split(":")[1]), (int(e.split(":")[2]), int(e.split(":")[3])))
                  for e in args.extra]
         res = multi_sweep(packet_set(args.n, args.draws), args.T, args.dt0, tol=args.tol, chunk=args.chunk,
