@@ -309,9 +309,12 @@ __device__ __forceinline__ void block_map(bool row, int e, int& s, int& w, int& 
 }
 
 // Line operation request of the propagation machine.
-// The operand is x = scale * (src + src2 - sum_{i<K} coef_i basis_i) (src2 may be null,
-// coef in LDS); row and column blocks form it with the same operations, so both see
-// the same values, and row blocks store it to copy_dst.
+// The operand is x = scale * (src + src2 - i hal (h1 + h2) - sum_{i<K} coef_i basis_i)
+// (src2, h1, h2 may be null, coef in LDS); row and column blocks form it with the same
+// operations, so both see the same values, and row blocks store it to copy_dst.  The
+// h term forms (1 - i al H) b from b and the two halves of H b (or a stored H b), so a
+// GMRES guess or a trapezoidal right-hand side needs no pass and no grid barrier of
+// its own.
 struct LineReq {
   const cplx* src;
   const cplx* src2;
@@ -324,6 +327,9 @@ struct LineReq {
   cplx* out_r;       // rows:    A_2 A_2 x / (2 m_2) + (V - shift) x   |  A_2 x
   cplx* out_c;       // columns: A_1 A_1 x / (2 m_1)                   |  A_1 x
   double shift = 0.0;  // H - shift (Arnoldi only)
+  const cplx* h1 = nullptr;
+  const cplx* h2 = nullptr;
+  double hal = 0.0;
 };
 
 template <int NL>
@@ -358,6 +364,16 @@ __device__ void line_op(const LineReq& q, const Ctx2& c, const K2Args& a, const 
         for (int u = 0; u < EB; ++u) t[u] = q.src2[gi[u]];
 #pragma unroll
         for (int u = 0; u < EB; ++u) v[u] = cadd(v[u], t[u]);
+      }
+      if (q.h1) {
+#pragma unroll
+        for (int u = 0; u < EB; ++u) t[u] = q.h1[gi[u]];
+        if (q.h2) {
+#pragma unroll
+          for (int u = 0; u < EB; ++u) t[u] = cadd(t[u], q.h2[gi[u]]);
+        }
+#pragma unroll
+        for (int u = 0; u < EB; ++u) v[u] = csub(v[u], cmul_is(t[u], q.hal));
       }
       for (int k = 0; k < q.K; ++k) {
         const cplx* bk = q.basis + (size_t)k * E::VEC;
@@ -577,24 +593,24 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
     }
     return true;
   };
-  auto solve_begin = [&](const cplx* b, cplx* x, double alv, int ret) -> bool {
+  // start a solve of (1 + i al H) x = b: ask for H b.  |b| joins the first residual's
+  // reduction; pre (when given) forms b itself in that load as src - i al_b h_1 (+ h_2)
+  // and stores it to b, the trapezoid's right-hand side.
+  auto solve_begin = [&](const cplx* b, cplx* x, double alv, int ret, const LineReq* pre = nullptr) {
     bg = b;
     xg = x;
     al = alv;
     after = ret;
     kind_mu = ret == k2AdjAfterMu;
     iters = 0;
-    double acc = 0.0;
-    for (long long e = e0 + threadIdx.x; e < e1; e += T) acc += cabs2(b[e]);
-    put_partial(c, 0, acc);
-    if (!gsum(1)) return false;
-    const double bnorm = sqrt(uniform_d(c.red[0]));
-    if (!isfinite(bnorm)) bad = true;
-    tolb = a.sc.tol * bnorm;
-    bnrm = bnorm;
-    request(b, true);
+    if (pre) {
+      rq = *pre;
+      pending = true;
+      swap_after = true;
+    } else {
+      request(b, true);
+    }
     pc = k2SolveGuess;
-    return true;
   };
   auto solve_end = [&](bool conv) {
     // the two groups of a reverse sweep interleave: phi solves even, mu solves odd
@@ -702,19 +718,13 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         break;
       }
       case k2TrapHpsi: {
+        // b = (1 - i alpha H) psi, formed and stored by the load of H b
         const bool fresh = literal || !have_hpsi;
-        for (long long e = e0 + threadIdx.x; e < e1; e += T) {
-          cplx h;
-          if (fresh) {
-            h = cadd(OR[e], OC[e]);
-            HP[e] = h;
-          } else {
-            h = HP[e];
-          }
-          B[e] = csub(psi[e], cmul_is(h, alpha));  // b = (1 - i alpha H) psi
-        }
-        touched = true;
-        solve_begin(B, psi, alpha, k2TrapAfter);
+        LineReq pre{psi, nullptr, nullptr, 0, mk(1.0, 0.0), false, B, true, ORs, OCs};
+        pre.h1 = fresh ? OR : HP;
+        pre.h2 = fresh ? OC : nullptr;
+        pre.hal = alpha;
+        solve_begin(B, psi, alpha, k2TrapAfter, &pre);
         break;
       }
       case k2TrapAfter: {
@@ -748,22 +758,35 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         break;
       }
       case k2SolveGuess: {
-        for (long long e = e0 + threadIdx.x; e < e1; e += T)
-          xg[e] = csub(bg[e], cmul_is(cadd(OR[e], OC[e]), al));  // x0 = (1 - i al H) b
-        touched = true;
-        request(xg, true);
+        // x0 = (1 - i al H) b, formed and stored by the load of H x0
+        rq = LineReq{bg, nullptr, nullptr, 0, mk(1.0, 0.0), false, xg, true, ORs, OCs};
+        rq.h1 = OR;
+        rq.h2 = OC;
+        rq.hal = al;
+        pending = true;
+        swap_after = true;
         pc = k2SolveResid;
         break;
       }
       case k2SolveResid: {
-        double acc = 0.0;
+        double acc = 0.0, accb = 0.0;
         for (long long e = e0 + threadIdx.x; e < e1; e += T) {
-          const cplx r = csub(bg[e], cadd(xg[e], cmul_is(cadd(OR[e], OC[e]), al)));  // b - X x
+          const cplx bv = bg[e];
+          const cplx r = csub(bv, cadd(xg[e], cmul_is(cadd(OR[e], OC[e]), al)));  // b - X x
           W[e] = r;
           acc += cabs2(r);
+          accb += cabs2(bv);
         }
         put_partial(c, 0, acc);
-        if (!gsum(1)) break;
+        put_partial(c, 1, accb);
+        if (!gsum(2)) break;
+        const double bnorm = sqrt(uniform_d(c.red[1]));
+        if (!isfinite(bnorm)) {
+          bad = true;
+          break;
+        }
+        tolb = a.sc.tol * bnorm;
+        bnrm = bnorm;
         const double beta = sqrt(uniform_d(c.red[0]));
         if (!isfinite(beta)) {
           bad = true;
