@@ -107,6 +107,27 @@ def test_composed_propagation_matches_oracle(gqd, scheme, order):
     assert abs(st.iterations - total_iters) <= max(2, total_iters // 50)
 
 
+def test_optimal_compositions_per_item_steps_and_trapezoid_match_oracle(gqd):
+    # the non-recursive schemes under both base methods, each item with its own step and
+    # step count in one launch (the library's own fractions against the oracle's
+    # published ones; they agree to 3e-10 at tenth order, which moves a state by ~1e-13)
+    items = items_for([256, 512, 1024], seed=8)
+    cases = [("trap", 6, 12.0, 3), ("midp", 8, 8.0, 2), ("trap", 10, 20.0, 1)]
+    opts = dict(tol=1e-14, restart=32)
+    for method, order, dt, nsteps in cases:
+        prop = gqd.from_items(items)
+        psi = prop.pack([it.psi0 for it in items])
+        dts = [dt, 0.5 * dt, 2.0 * dt]
+        steps = [nsteps, 2 * nsteps, 1]
+        prop.propagate_items(psi, method, "optimal", order, dts, steps, gqd.SolverOpts(**opts))
+        for it, out, d, n in zip(items, prop.unpack(psi), dts, steps):
+            ref = O.propagate(O.model_from_item(it), it.psi0, O.TRAP if method == "trap" else O.MIDP,
+                              O.OPTIMAL, order, d, n, O.SolverOpts(**opts))
+            print(f"optimal-{order} {method} n={it.n} dt={d} x{n}: rel {rel(out, ref):.2e}", flush=True)
+            assert rel(out, ref) <= 1e-12
+        prop.close()
+
+
 def test_trapezoid_trajectory_matches_oracle(gqd):
     # moving packet, 400 trapezoidal steps of 10 a.u. solved to stagnation (tol 1e-15):
     # the solver tolerance no longer separates the two sides, only roundoff does
