@@ -213,6 +213,7 @@ class SolverOpts:
     maxit: int = 1000      # total Arnoldi iterations allowed per solve
     literal: bool = False  # True: perform every explicit half-step (3 + I applies)
     verify: bool = False   # True: confirm convergence on the true residual (restart if not met)
+    precond: bool = False  # True: right-precondition by the exact inverse of 1 + i a T
 
 
 @dataclass
@@ -257,13 +258,17 @@ def givens(a: complex, b: float) -> Tuple[float, complex, complex]:
 
 
 def gmres(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, x0: np.ndarray,
-          tol: float, m: int, maxit: int, verify: bool = False) -> Tuple[np.ndarray, SolveInfo]:
+          tol: float, m: int, maxit: int, verify: bool = False,
+          prec: Optional[Callable[[np.ndarray], np.ndarray]] = None) -> Tuple[np.ndarray, SolveInfo]:
     """Restarted GMRES(m) (Saad & Schultz) for A x = b from x0 (Sec. II.C).
 
     Arnoldi with modified Gram-Schmidt, least squares by Givens rotations; the stop
     rule is the residual estimate |g_{j+1}| <= tol * ||b||.  With verify, a solve that
     meets it forms x and ends only if the true residual |b - A x| meets the tolerance
-    as well; otherwise GMRES restarts from that x."""
+    as well; otherwise GMRES restarts from that x.  With prec (x -> M^-1 x), GMRES is
+    right-preconditioned: the Arnoldi process runs on A M^-1 and the cycle's update is
+    M^-1 V y, so the residual it minimises and tests is still that of A x = b."""
+    P = prec if prec is not None else (lambda v: v)
     bnorm = float(np.linalg.norm(b))
     x = x0.copy()
     iters = 0
@@ -284,7 +289,7 @@ def gmres(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, x0: np.ndar
         k = 0
         converged = False
         for j in range(m):
-            w = matvec(basis[j])
+            w = matvec(P(basis[j]))
             iters += 1
             for i in range(j + 1):                      # modified Gram-Schmidt
                 R[i, j] = np.vdot(basis[i], w)
@@ -309,7 +314,7 @@ def gmres(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, x0: np.ndar
         y = np.zeros(k, dtype=np.complex128)
         for i in range(k - 1, -1, -1):                  # back substitution R y = g
             y[i] = (g[i] - np.dot(R[i, i + 1:k], y[i + 1:k])) / R[i, i]
-        x = x + basis[:k].T @ y
+        x = x + P(basis[:k].T @ y)
         if converged and not verify:
             return x, SolveInfo(iters, True)
 
@@ -325,6 +330,26 @@ def explicit_euler(model: Model, psi: np.ndarray, eps: float,
     return psi - 1j * eps * hpsi
 
 
+def kinetic_inverse(model: Model, eps: float) -> Callable[[np.ndarray], np.ndarray]:
+    """x -> (1 + i eps T)^-1 x with T = sum_d p_d^2 / 2 m_d, exactly, in momentum space
+    (forward DFT along every nuclear axis, division, inverse DFT), the same operator on
+    both surfaces: a right preconditioner for 1 + i eps H, whose kinetic part it inverts
+    (the coupling and the potential are left to GMRES)."""
+    T = np.zeros(model.shape[1:], dtype=np.float64)
+    for d in range(model.D):
+        p = momentum_grid(model.n[d], model.qmax[d] - model.qmin[d])
+        sh = [1] * model.D
+        sh[d] = model.n[d]
+        T = T + (p.reshape(sh) ** 2) / (2.0 * model.mass[d])
+    den = 1.0 + 1j * eps * T
+    axes = tuple(range(1, model.D + 1))
+
+    def apply(x: np.ndarray) -> np.ndarray:
+        return np.fft.ifftn(np.fft.fftn(x, axes=axes) / den[None], axes=axes)
+
+    return apply
+
+
 def implicit_euler(model: Model, psi: np.ndarray, eps: float, opts: SolverOpts,
                    stats: Optional[Stats] = None) -> np.ndarray:
     """U_impl(eps) psi = (1 + i eps H)^-1 psi, Eq. (14), by GMRES with the explicit-Euler
@@ -337,7 +362,9 @@ def implicit_euler(model: Model, psi: np.ndarray, eps: float, opts: SolverOpts,
         return v + 1j * eps * apply_H(model, v.reshape(shape), counter).ravel()
 
     x0 = explicit_euler(model, psi, eps, counter)
-    x, info = gmres(matvec, psi.ravel(), x0.ravel(), opts.tol, opts.restart, opts.maxit, opts.verify)
+    prec = kinetic_inverse(model, eps) if opts.precond else None
+    x, info = gmres(matvec, psi.ravel(), x0.ravel(), opts.tol, opts.restart, opts.maxit, opts.verify,
+                    None if prec is None else (lambda v: prec(v.reshape(shape)).ravel()))
     stats.record(info)
     stats.h_applies += counter.h_applies
     return x.reshape(shape)

@@ -59,6 +59,7 @@ struct gqd_handle {
   double* d_part = nullptr;
   int resident_cap = 0;  // workgroups the partial and sync areas are sized for
   int stats_roles = 1;   // groups per item of the last 2D launch (2: merge their statistics)
+  int stats_precond = 0; // the last launch's solves were preconditioned (byte count)
   int spin_limit = 0;    // polls of a 2D grid wait before it gives up (0: the default)
   std::vector<ItemMeta> items;
   long long total_complex = 0;
@@ -90,7 +91,9 @@ gqd_status check_opts(const gqd_handle* h, const gqd_solver_opts* o) {
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(GQD_ERR_INVALID, "tol must be finite and > 0");
   if (o->restart < 1 || o->restart > kMaxRestart) return fail(GQD_ERR_INVALID, "restart must be in 1..64");
   if (o->maxit < 1) return fail(GQD_ERR_INVALID, "maxit must be >= 1");
+  if (o->precond != 0 && o->precond != 1) return fail(GQD_ERR_INVALID, "precond must be 0 or 1");
   if (h->dims == 2) {
+    if (o->precond) return fail(GQD_ERR_UNSUPPORTED, "the kinetic preconditioner is available on 1D grids");
     if (lds_bytes2(h->n2, o->restart) > kLdsMax)
       return fail(GQD_ERR_UNSUPPORTED, "restart " + std::to_string(o->restart) +
                                            " needs more than 160 KB of LDS at n = " + std::to_string(h->n2) +
@@ -342,10 +345,13 @@ gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
     st->failures += s.failures;
     st->nonfinite += s.nonfinite;
     if (s.max_resid > st->max_true_resid) st->max_true_resid = s.max_resid;
-    // 32 (I^2 + 4 I + 8) bytes per grid point per solve (S = 2 complex128 vectors)
+    // 32 (I^2 + 4 I + 8) bytes per grid point per solve (S = 2 complex128 vectors);
+    // preconditioned: each iteration also writes and reads z_j = M^-1 v_j, and the
+    // cycle's update passes V y through M^-1: 32 (I^2 + 6 I + 10)
     const double pts = h->dims == 2 ? (double)h->n2 * h->n2 : (double)h->items[b].n;
+    const double per_it = h->stats_precond ? 6.0 : 4.0, per_solve = h->stats_precond ? 10.0 : 8.0;
     st->alg_bytes += 32.0 * pts *
-                     ((double)s.iterations_sq + 4.0 * (double)s.iterations + 8.0 * (double)s.solves);
+                     ((double)s.iterations_sq + per_it * (double)s.iterations + per_solve * (double)s.solves);
     if ((s.failures || s.nonfinite) && st->failed_item < 0) st->failed_item = b;
   }
   for (int b = 0; b < h->batch; ++b)
@@ -659,7 +665,8 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
     a.mode = kM2Propagate;
     a.psi = (double2*)psi;
     a.work = (double2*)h->work;
-    a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
+    a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
+    h->stats_precond = a.sc.precond;
     a.method = (m == GQD_TRAP) ? kTrap : kMidp;
     a.dt = dt;
     a.nsteps = nsteps;
@@ -673,7 +680,8 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   if (s != GQD_OK) return s;
   a.psi = (double2*)psi;
   a.work = (double2*)h->work;
-  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
+  h->stats_precond = a.sc.precond;
   a.mode = 0;
   a.method = method_code(m);
   a.dt = dt;
@@ -718,7 +726,8 @@ gqd_status gqd_propagate_noalloc(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   if (s != GQD_OK) return s;
   a.psi = (double2*)psi;
   a.work = (double2*)h->scratch;  // nothing in the scratch is read before it is written
-  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
+  h->stats_precond = a.sc.precond;
   a.mode = 0;
   a.method = method_code(m);
   a.dt = dt;
@@ -851,7 +860,8 @@ gqd_status gqd_autotune(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, 
   if (s != GQD_OK) return s;
   a.psi = (double2*)psi;
   a.work = (double2*)h->work;
-  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
+  h->stats_precond = a.sc.precond;
   a.mode = 0;
   a.method = (m == GQD_TRAP) ? kTrap : kMidp;
   a.dt = dt;
@@ -924,7 +934,8 @@ gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long
     a.aux = (double2*)lambda;
     a.gF = gF;
     a.work = (double2*)h->work;
-    a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
+    a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
+    h->stats_precond = a.sc.precond;
     a.dt = dt;
     a.nsteps = nsteps;
     hipStream_t strm = (hipStream_t)stream;
@@ -939,7 +950,8 @@ gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long
   a.aux = (double2*)lambda;
   a.gF = gF;
   a.work = (double2*)h->work;
-  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0};
+  a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
+  h->stats_precond = a.sc.precond;
   a.dt = dt;
   a.nsteps = nsteps;
   hipStream_t strm = (hipStream_t)stream;

@@ -53,6 +53,7 @@ struct SolveCfg {
   int literal;  // 1: perform every explicit half-step
   int verify;   // 1: a solve that converges by its residual estimate ends only once
                 // its true residual meets the tolerance (else GMRES restarts from x)
+  int precond;  // 1: GMRES right-preconditioned by (1 + i a p^2 / 2m)^-1 (1D)
 };
 
 // Composition coefficients per recursion level l (raising order 2l+2 to 2l+4).  Both

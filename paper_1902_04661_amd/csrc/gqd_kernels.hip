@@ -363,9 +363,10 @@ struct Eng {
   // Fused last forward pass (radix RF, Ns = N/RF), momentum multiply and first
   // inverse pass (radix RF, Ns = 1): butterfly j's forward outputs are the k-space
   // points j + r N/RF, exactly the inputs of the inverse butterfly j.
-  // KEXP: multiply by exp(-i ktau p_k^2) / N (the kinetic factor of a split-operator
-  // step, ktau = tau / 2m) instead of p_k / N
-  template <bool KEXP = false, class Next>
+  // KM = 1: multiply by exp(-i ktau p_k^2) / N (the kinetic factor of a split-operator
+  // step, ktau = tau / 2m); KM = 2: by (1 + i ktau p_k^2)^-1 / N (the inverse of the
+  // kinetic part of 1 + i a H, ktau = a / 2m); KM = 0: by p_k / N
+  template <int KM = 0, class Next>
   static __device__ __forceinline__ void fused_kspace(const GQD_L cplx* src, GQD_L cplx* dst,
                                                       const TwS<RF, N / RF>& tw, const Ctx& c, Next&& next,
                                                       double ktau = 0.0) {
@@ -396,11 +397,17 @@ struct Eng {
       for (int r = 0; r < RF; ++r) {
         const int kk = j + r * Ns;                      // k-space index
         const int kp = (kk < N / 2) ? kk : kk - N;      // signed wavenumber
-        if constexpr (KEXP) {
+        if constexpr (KM == 1) {
           const double pk = scale * (double)N * (double)kp;
           double sn, cs;
           sincos(-ktau * pk * pk, &sn, &cs);
           x[q][r] = cscale(cmul(x[q][r], mk(cs, sn)), 1.0 / (double)N);
+        } else if constexpr (KM == 2) {
+          // (1 + i ktau p^2)^-1 / N = (1 - i q) / (N (1 + q^2)), q = ktau p^2
+          const double pk = scale * (double)N * (double)kp;
+          const double qk = ktau * pk * pk;
+          const double inv = 1.0 / ((double)N * (1.0 + qk * qk));
+          x[q][r] = mk((x[q][r].x + qk * x[q][r].y) * inv, (x[q][r].y - qk * x[q][r].x) * inv);
         } else {
           x[q][r] = cscale(x[q][r], scale * (double)kp);  // p_k / N
         }
@@ -498,7 +505,7 @@ struct Eng {
   // Fused last forward pass (radix RF, Ns = M/RF, table TP), k-space factor and first
   // inverse pass (radix RF, Ns = 1) over the wave's slabs: forward output r of butterfly
   // j of slab e is X[k1 + R0 (j + r M/RF)]; the inverse writes y[e M + j RF + r] through swz.
-  template <bool KEXP, int TP, bool SWIN>
+  template <int KM, int TP, bool SWIN>
   static __device__ __forceinline__ void wfused(const GQD_L cplx* src, GQD_L cplx* dst, const Ctx& c,
                                                 int slab0, double ktau) {
     constexpr int NR = M / RF;
@@ -540,11 +547,17 @@ struct Eng {
         for (int r = 0; r < RF; ++r) {
           const int kk = k1 + R0 * (j + r * NR);          // k-space index
           const int kp = (kk < N / 2) ? kk : kk - N;      // signed wavenumber
-          if constexpr (KEXP) {
+          if constexpr (KM == 1) {
             const double pk = scale * (double)N * (double)kp;
             double sn, cs;
             sincos(-ktau * pk * pk, &sn, &cs);
             x[q][r] = cscale(cmul(x[q][r], mk(cs, sn)), 1.0 / (double)N);
+          } else if constexpr (KM == 2) {
+            // (1 + i ktau p^2)^-1 / N = (1 - i q) / (N (1 + q^2)), q = ktau p^2
+            const double pk = scale * (double)N * (double)kp;
+            const double qk = ktau * pk * pk;
+            const double inv = 1.0 / ((double)N * (1.0 + qk * qk));
+            x[q][r] = mk((x[q][r].x + qk * x[q][r].y) * inv, (x[q][r].y - qk * x[q][r].x) * inv);
           } else {
             x[q][r] = cscale(x[q][r], scale * (double)kp);  // p_k / N
           }
@@ -562,7 +575,7 @@ struct Eng {
       }
     }
   }
-  template <bool KEXP = false>
+  template <int KM = 0>
   static __device__ void kinetic_fs(const OV& x, OV& u, const Ctx& c, double ktau) {
     GQD_L cplx* b0 = c.fft;                          // forward exchange
     GQD_L cplx* b1 = kPP ? c.fft + 2 * N : c.fft;    // slab work and the way back
@@ -593,7 +606,7 @@ struct Eng {
     if constexpr (R3 == 1) {
       wpass<R1, 1, -1, -1, false, true, false>(X, Y, c, slab0);
       wave_sync();
-      wfused<KEXP, 1, true>(Y, Y, c, slab0, ktau);
+      wfused<KM, 1, true>(Y, Y, c, slab0, ktau);
       wave_sync();
       wpass<R1, R2, +1, 2, true, false, true>(Y, Y, c, slab0);
     } else {
@@ -601,7 +614,7 @@ struct Eng {
       wave_sync();
       wpass<R2, R1, -1, 1, true, false, false>(Y, Y, c, slab0);
       wave_sync();
-      wfused<KEXP, 2, false>(Y, Y, c, slab0, ktau);
+      wfused<KM, 2, false>(Y, Y, c, slab0, ktau);
       wave_sync();
       wpass<R2, R3, +1, 3, true, false, false>(Y, Y, c, slab0);
       wave_sync();
@@ -623,18 +636,19 @@ struct Eng {
   }
 
   // u = p x on both surfaces (forward DFT, multiply by p_k, inverse DFT / N); with
-  // KEXP, u = exp(-i ktau p^2) x instead (the kinetic factor of a split-operator step).
-  template <bool KEXP = false>
+  // KM = 1, u = exp(-i ktau p^2) x instead (the kinetic factor of a split-operator step),
+  // with KM = 2, u = (1 + i ktau p^2)^-1 x (the GMRES preconditioner).
+  template <int KM = 0>
   static __device__ void kinetic(const OV& x, OV& u, const Ctx& c, double ktau = 0.0) {
     if constexpr (kFS) {
-      kinetic_fs<KEXP>(x, u, c, ktau);
+      kinetic_fs<KM>(x, u, c, ktau);
     } else {
-      kinetic_sh<KEXP>(x, u, c, ktau);
+      kinetic_sh<KM>(x, u, c, ktau);
     }
   }
 
   // Stockham form: every pass over the whole transform, one barrier each
-  template <bool KEXP = false>
+  template <int KM = 0>
   static __device__ void kinetic_sh(const OV& x, OV& u, const Ctx& c, double ktau = 0.0) {
     GQD_L cplx* b0 = c.fft;
     GQD_L cplx* b1 = kPP ? c.fft + 2 * N : c.fft;
@@ -657,7 +671,7 @@ struct Eng {
       TwS<RF, N / RF> tf;
       TwS<R1, R2> t2;
       pass<R1, R0, -1, true>(b0, b1, t0, [&] { tw_load<RF, N / RF, 1>(tf, opaque(c.tw)); });
-      fused_kspace<KEXP>(b1, b0, tf, c, [&] { tw_load<R1, R2, 2>(t2, opaque(c.tw)); }, ktau);
+      fused_kspace<KM>(b1, b0, tf, c, [&] { tw_load<R1, R2, 2>(t2, opaque(c.tw)); }, ktau);
       pass<R1, R2, +1, true>(b0, b1, t2, [&] { tw_load<R0, T, PL>(tl, opaque(c.tw)); });
     } else {
       TwS<R2, R0 * R1> t1;
@@ -666,7 +680,7 @@ struct Eng {
       TwS<R1, R3 * R2> t4;
       pass<R1, R0, -1, true>(b0, b1, t0, [&] { tw_load<R2, R0 * R1, 1>(t1, opaque(c.tw)); });
       pass<R2, R0 * R1, -1>(b1, b0, t1, [&] { tw_load<RF, N / RF, 2>(tf, opaque(c.tw)); });
-      fused_kspace<KEXP>(b0, b1, tf, c, [&] { tw_load<R2, R3, 3>(t3, opaque(c.tw)); }, ktau);
+      fused_kspace<KM>(b0, b1, tf, c, [&] { tw_load<R2, R3, 3>(t3, opaque(c.tw)); }, ktau);
       pass<R2, R3, +1, true>(b1, b0, t3, [&] { tw_load<R1, R3 * R2, 4>(t4, opaque(c.tw)); });
       pass<R1, R3 * R2, +1>(b0, b1, t4, [&] { tw_load<R0, T, PL>(tl, opaque(c.tw)); });
     }
@@ -858,7 +872,10 @@ enum Pc {
   kImplAfter,     // implicit Euler: x solved
   kSodStart,      // second-order differencing: have H psi(0)
   kSodStart2,     // second-order differencing: have H H psi(0)
-  kSodStep        // second-order differencing: have H psi(t)
+  kSodStep,       // second-order differencing: have H psi(t)
+  kPrecZ,         // preconditioned GMRES: have z_j = M^-1 v_j, ask for H z_j
+  kPrecArnoldi,   // preconditioned GMRES: have H z_j: Arnoldi step j on X M^-1
+  kPrecUpdate     // preconditioned GMRES: have M^-1 V y: x += it
 };
 
 // Whole-call propagation (mode 0) or reverse sweep (mode 1) of one item per workgroup.
@@ -880,7 +897,9 @@ enum Pc {
 // Reverse sweep, substeps in reverse order: phi = (1 - i alpha H)^-1 psi,
 // mu = (1 - i alpha H)^-1 lambda, psi <- 2 phi - psi, lambda <- 2 mu - lambda,
 // gF += -(2 alpha / m) Re[conj(mu1)(A phi)2 - conj(mu2)(A phi)1 + conj(A mu)1 phi2 - conj(A mu)2 phi1].
-template <int P>
+// PC: the solves are right-preconditioned (a separate instantiation, so that the plain
+// solver's register allocation does not carry the preconditioned states)
+template <int P, bool PC = false>
 __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(Eng<P>::WPE))) k_run(KArgs a) {
   using E = Eng<P>;
   constexpr int N = E::N;
@@ -919,8 +938,11 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
   double alpha = 0.0;  // half the substep (geometric methods), the whole step (elementary)
   bool sod_started = false;
 
-  // operator request: H - opshift applied to opsrc (opshift = 0 outside Arnoldi)
-  bool pending = false, opH = false, op_in_y = false;
+  // operator request: H - opshift applied to opsrc (opshift = 0 outside Arnoldi), or
+  // (opK) the preconditioner (1 + i ktau p^2)^-1, one transform pair, no coupling
+  bool pending = false, opH = false, op_in_y = false, opK = false;
+  double opktau = 0.0;
+  bool prec_cv = false;  // preconditioned cycle: converged by the estimate
   bool psi_in_y = false;  // y holds psi at owned points (set by the midpoint update)
   int half = 0;
   const cplx* opsrc = nullptr;
@@ -953,6 +975,18 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
     opH = h;
     opshift = shift;
     op_in_y = in_y;
+    opK = false;
+    half = 0;
+  };
+  // the preconditioner M^-1 = (1 + i al p^2 / 2m)^-1 of the current solve on y
+  auto request_prec = [&]() {
+    pending = true;
+    opsrc = nullptr;
+    opH = false;
+    opshift = 0.0;
+    op_in_y = true;
+    opK = true;
+    opktau = al * a.inv2m;
     half = 0;
   };
   // start a solve of (1 + i al H) x = b: ||b||, then ask for H b.  b_in_y: y holds b
@@ -1000,6 +1034,13 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
 
   for (;;) {
     if (bad) break;
+    if constexpr (PC) {
+      if (pending && opK) {
+        // (the transform reads all of its input before it writes any of its output)
+        E::template kinetic<2>(y, y, c, opktau);
+        pending = false;
+      }
+    }
     if (pending) {
       // one transform per turn: turn 1 takes the input from opsrc, turn 2 (H only) takes
       // chi = A x from registers; x and then the partial result are kept in registers
@@ -1180,8 +1221,120 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         if (threadIdx.x == 0) c.g[0] = mk(beta, 0.0);
         // (the next block reduction's barrier orders this write before any read)
         j = 0;
+        if constexpr (PC) {
+          request_prec();
+          pc = kPrecZ;
+          break;
+        }
         request(basis, true, kind_mu ? sig1 : sig0, true);
         pc = kSolveArnoldi;
+        break;
+      }
+      case kPrecZ: {
+        if constexpr (PC) {
+          // z_j = M^-1 v_j in y: kept in S3 for w = X z_j, then H z_j
+          E::store(y, S3);
+          request(S3, true, 0.0, true);
+          pc = kPrecArnoldi;
+          break;
+        }
+        break;
+      }
+      case kPrecArnoldi: {
+        if constexpr (PC) {
+          // Arnoldi step j on X M^-1 (right preconditioning): w = z_j + i al H z_j, one
+          // classical Gram-Schmidt pass over v_0..v_j with |w|^2 from the same reduction,
+          // a second pass when the first keeps less than kReorthRatio of |w|^2.  X M^-1
+          // has no Hermitian structure to exploit, and the column is X M^-1's own.
+          ++iters;
+          {
+            OV z;
+            E::load(z, S3);
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+              for (int r = 0; r < R0; ++r) y.v[s][r] = cadd(z.v[s][r], cmul_is(y.v[s][r], al));
+          }
+          E::template block_dots<E::kStashOff>(basis, y, j + 1, c, c.hcol, true);
+          const double w2 = uniform_d(c.hcol[j + 1].x);
+          double hn2 = w2;
+          for (int i = 0; i <= j; ++i) hn2 -= cabs2(c.hcol[i]);
+          hn2 = uniform_d(hn2);
+          E::template block_axpy<false>(basis, c.hcol, j + 1, y, c);
+          if (hn2 < kReorthRatio * w2) {
+            E::template block_dots<E::kStashOff>(basis, y, j + 1, c, c.y, true);
+            double r2 = uniform_d(c.y[j + 1].x);
+            for (int i = 0; i <= j; ++i) r2 -= cabs2(c.y[i]);
+            hn2 = uniform_d(r2 > 0.0 ? r2 : 0.0);
+            E::template block_axpy<false>(basis, c.y, j + 1, y, c);
+            // every wave has read the pass's coefficients before the column gains them
+            __syncthreads();
+            for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);
+          }
+          __syncthreads();
+          const double hn = sqrt(hn2);
+          E::givens_update(j, hn, c);
+          const double gabs = uniform_d(c.scal[0]);
+          if (!isfinite(hn) || !isfinite(gabs)) {
+            bad = true;
+            break;
+          }
+          const bool cv = gabs <= tolb;
+          if (!cv && hn != 0.0 && iters < a.sc.maxit && j + 1 < m) {
+            const double sc = 1.0 / hn;
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+              for (int r = 0; r < R0; ++r) y.v[s][r] = cscale(y.v[s][r], sc);
+            ++j;
+            E::store(y, basis + (size_t)j * E::VEC);
+            request_prec();
+            pc = kPrecZ;
+            break;
+          }
+          // cycle ends: x += M^-1 (V y) over the k = j + 1 basis vectors
+          const int k = j + 1;
+          E::back_solve(k, c);
+#pragma unroll
+          for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) y.v[s][r] = mk(0.0, 0.0);
+          for (int i = 0; i < k; ++i) {
+            OV v;
+            E::load(v, basis + (size_t)i * E::VEC);
+            const cplx yi = c.y[i];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+              for (int r = 0; r < R0; ++r) y.v[s][r] = cadd(y.v[s][r], cmul(yi, v.v[s][r]));
+          }
+          __syncthreads();  // c.y is read by all before it can be rewritten
+          prec_cv = cv;
+          request_prec();
+          pc = kPrecUpdate;
+          break;
+        }
+        break;
+      }
+      case kPrecUpdate: {
+        if constexpr (PC) {
+          {
+            OV x;
+            E::load(x, xg);
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+              for (int r = 0; r < R0; ++r) x.v[s][r] = cadd(x.v[s][r], y.v[s][r]);
+            E::store(x, xg);
+          }
+          if (prec_cv && !a.sc.verify) {
+            solve_end(true);
+          } else {  // verification, restart, or maxit / breakdown: the true residual decides
+            request(xg, true);
+            pc = kSolveResid;
+          }
+          break;
+        }
         break;
       }
       case kSolveArnoldi: {
@@ -1488,7 +1641,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
       const double tau = substep_tau(cc, a.gt) * dt;
       E::expW(y, 0.5 * tau, c);
       t = y;
-      E::template kinetic<true>(t, y, c, tau * c.inv2m);
+      E::template kinetic<1>(t, y, c, tau * c.inv2m);
       E::expW(y, 0.5 * tau, c);
     }
   }
@@ -1595,7 +1748,8 @@ template <int P>
 static hipError_t set_lds_limit(size_t bytes) {
   hipError_t e;
   if ((e = hipFuncSetAttribute((const void*)k_apply_h<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_run<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_run<P, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_run<P, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_diag<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)k_split<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_inner<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -1648,7 +1802,16 @@ hipError_t configure_kernels(int m_max) {
   return hipGetLastError();
 
 hipError_t launch_apply_h(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_apply_h, 0) }
-hipError_t launch_run(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_run, a.sc.m) }
+hipError_t launch_run(int plan, const KArgs& a, hipStream_t stream) {
+  GQD_DISPATCH(plan, {
+    if (a.nlist <= 0) return hipSuccess;
+    if (a.sc.precond)
+      hipLaunchKernelGGL((k_run<P, true>), dim3(a.nlist), dim3(Eng<P>::T), lds_bytes(P, a.sc.m), stream, a);
+    else
+      hipLaunchKernelGGL((k_run<P, false>), dim3(a.nlist), dim3(Eng<P>::T), lds_bytes(P, a.sc.m), stream, a);
+  });
+  return hipGetLastError();
+}
 hipError_t launch_diag(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_diag, 0) }
 hipError_t launch_split(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_split, 0) }
 hipError_t launch_inner(int plan, const KArgs& a, hipStream_t stream) { GQD_LAUNCH(k_inner, 0) }

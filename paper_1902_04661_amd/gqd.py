@@ -53,7 +53,7 @@ class _GridDesc(ctypes.Structure):
 
 class _SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
-                ("literal", ctypes.c_int), ("verify", ctypes.c_int)]
+                ("literal", ctypes.c_int), ("verify", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -134,10 +134,11 @@ class SolverOpts:
     maxit: int = 1000
     literal: bool = False
     verify: bool = False  # end a solve only on a true residual within tol (restart otherwise)
+    precond: bool = False  # right-precondition GMRES by (1 + i a p^2 / 2m)^-1 (1D)
 
     def c(self) -> _SolverOpts:
         return _SolverOpts(float(self.tol), int(self.restart), int(self.maxit), int(bool(self.literal)),
-                           int(bool(self.verify)))
+                           int(bool(self.verify)), int(bool(self.precond)))
 
 
 @dataclass

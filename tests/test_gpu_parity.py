@@ -128,6 +128,62 @@ def test_optimal_compositions_per_item_steps_and_trapezoid_match_oracle(gqd):
         prop.close()
 
 
+@pytest.mark.parametrize("method", ["midp", "trap"])
+def test_preconditioned_propagation_matches_oracle(gqd, method):
+    # GMRES right-preconditioned by (1 + i a p^2 / 2m)^-1 on both sides, every size class
+    # in one call
+    items = items_for(SIZES, seed=9)
+    prop = gqd.from_items(items)
+    psi = prop.pack([it.psi0 for it in items])
+    opts = dict(tol=1e-14, restart=32, precond=True)
+    st = prop.propagate(psi, method, "suzuki", 4, 10.0, 2, gqd.SolverOpts(**opts))
+    total = 0
+    for it, out in zip(items, prop.unpack(psi)):
+        ost = O.Stats()
+        ref = O.propagate(O.model_from_item(it), it.psi0, O.MIDP if method == "midp" else O.TRAP,
+                          O.SUZUKI, 4, 10.0, 2, O.SolverOpts(**opts), ost)
+        total += ost.iterations
+        print(f"preconditioned {method} n={it.n}: rel {rel(out, ref):.2e}, oracle iterations per solve "
+              f"{ost.iterations / ost.solves:.2f}", flush=True)
+        assert rel(out, ref) <= 1e-12
+    print(f"Arnoldi iterations: gpu {st.iterations} oracle {total}", flush=True)
+    assert abs(st.iterations - total) <= max(2, total // 50)
+    prop.close()
+
+
+def test_preconditioned_restarts_verify_and_adjoint_match_oracle(gqd):
+    it = I.nai_like_item(1024, q0=4.6, p0=-4.0, amp=0.7)
+    m = O.model_from_item(it)
+    # GMRES(2) with verification: every cycle ends through M^-1 V y and a true residual
+    opts = dict(tol=1e-14, restart=2, maxit=4000, precond=True, verify=True)
+    prop = gqd.from_items([it])
+    psi = prop.pack([it.psi0])
+    st = prop.propagate(psi, "midp", "suzuki", 4, 8.0, 2, gqd.SolverOpts(**opts))
+    ost = O.Stats()
+    ref = O.propagate(m, it.psi0, O.MIDP, O.SUZUKI, 4, 8.0, 2, O.SolverOpts(**opts), ost)
+    out = prop.unpack(psi)[0]
+    print(f"preconditioned GMRES(2), verified: rel {rel(out, ref):.2e}, iterations gpu {st.iterations} "
+          f"oracle {ost.iterations}, max true residual {st.max_true_resid:.1e}", flush=True)
+    assert rel(out, ref) <= 1e-12 and st.failures == 0
+    assert st.max_true_resid <= 1e-14
+    # reverse sweep with preconditioned solves, from the oracle's psi(T) and lambda(T)
+    aopts = dict(tol=1e-14, restart=32, precond=True)
+    oT = O.propagate(m, it.psi0, O.MIDP, O.SUZUKI, 4, 8.0, 3, O.SolverOpts(**aopts))
+    lT = O.population_loss(m, oT)[1]
+    po, lo, go = O.adjoint(m, oT, lT, O.SUZUKI, 4, 8.0, 3, O.SolverOpts(**aopts))
+    psi = prop.pack([oT])
+    lam = prop.pack([lT])
+    gF = torch.zeros(prop.state_size // 2, dtype=torch.float64, device=prop.device)
+    prop.adjoint(psi, lam, gF, "suzuki", 4, 8.0, 3, gqd.SolverOpts(**aopts))
+    r_l = rel(prop.unpack(lam)[0], lo)
+    r_g = rel(gF.cpu().numpy(), go[0])
+    r_p = rel(prop.unpack(psi)[0], po)
+    print(f"preconditioned reverse sweep: lambda rel {r_l:.2e}, gF rel {r_g:.2e}, psi(0) rel {r_p:.2e}",
+          flush=True)
+    assert r_l <= 1e-10 and r_g <= 1e-10 and r_p <= 1e-12
+    prop.close()
+
+
 def test_trapezoid_trajectory_matches_oracle(gqd):
     # moving packet, 400 trapezoidal steps of 10 a.u. solved to stagnation (tol 1e-15):
     # the solver tolerance no longer separates the two sides, only roundoff does

@@ -234,3 +234,12 @@ def test_wait_limit_gives_up_and_recovers_2d(gqd):
     print(f"after the limit is restored: {st.solves} solves, max |diff| "
           f"{float((psi - ref).abs().max()):.1e}", flush=True)
     assert st.nonfinite == 0 and torch.equal(psi, ref)
+
+
+def test_preconditioner_is_rejected_on_2d_grids(gqd):
+    it = moving_item(64, seed=2, p0=(1.0, 0.0))
+    prop = gqd.from_items([it])
+    psi = prop.pack([it.psi0])
+    with pytest.raises(gqd.GqdError, match="1D grids"):
+        prop.propagate(psi, "midp", "suzuki", 2, 10.0, 1, gqd.SolverOpts(tol=1e-14, precond=True))
+    prop.close()
