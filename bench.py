@@ -17,11 +17,15 @@ compositions of orders 8 and 10 (2.5 and 10 a.u.) on the same batch, each at its
 256..4096, Suzuki order 6 at its verified step 2.5 a.u.); 1D and 2D gradients; the 2D
 model; the elementary and diabatic controls.
 
+Solver: GMRES right-preconditioned by the exact inverse of the kinetic part of
+1 + i a H (option precond; about half the iterations of the plain GMRES at N = 2048,
+whose rate on the same batch is reported beside it as `plain_gmres`).
+
 Roofline: the propagation kernel against the HBM peak (8 TB/s) with algorithmic bytes
-32 (I^2 + 4I + 8) per grid point per substep for a solve of I Arnoldi iterations
-(S = 2 complex128 vectors, one Gram-Schmidt pass, fused H application), summed over
-the solves of one launch and divided by the launch's average duration (HIP events
-on the launch stream).  cpu_baseline: the CPU oracle on draws of the same batch, one
+32 (I^2 + 6I + 10) per grid point per substep for a preconditioned solve of I Arnoldi
+iterations (32 (I^2 + 4I + 8) for the plain one; S = 2 complex128 vectors, one
+Gram-Schmidt pass, fused H application), summed over the solves of one launch and
+divided by the launch's average duration (HIP events on the launch stream).  cpu_baseline: the CPU oracle on draws of the same batch, one
 packet per process on the host's cores, over a bounded sample.
 """
 from __future__ import annotations
@@ -51,23 +55,31 @@ DT_STAR_OPT8 = 2.5
 DT_STAR_OPT10 = 10.0
 TOL = 1e-17
 RAGGED_DT = 2.5
+# GMRES right-preconditioned by the exact inverse of the kinetic part of 1 + i a H (the
+# solver option precond, 1D): the same solutions to the solve tolerance in about half
+# the iterations at N = 2048 and 20 a.u.; the legs whose systems are not stiff (the
+# gradient at N = 1024 and 4 a.u., the diabatic comparison) and the 2D legs (no 2D
+# preconditioner) run the plain solver
+PRECOND = True
 # the 2D model and the 1D gradient workload run at their configurations' own steps
 DT_2D = 10.0
 TOL_2D = 1e-14
 TOL_ADJ = 1e-14
 
-# Memory traffic of the propagation kernel from two rocprofv3 --pmc passes (FETCH_SIZE, then
-# WRITE_SIZE) over one launch from t = 0 of this workload, scaled by what the counters read
-# for a 1 GiB device copy (FETCH_SIZE 0.5x, WRITE_SIZE 1.0x of the true bytes).  The
+# Memory traffic of the propagation kernel (the preconditioned solver) from two rocprofv3
+# --pmc passes (FETCH_SIZE, then WRITE_SIZE) over one launch from t = 0 of this workload,
+# scaled by what the counters read for a 1 GiB device copy (FETCH_SIZE 0.5x, WRITE_SIZE
+# 1.0x of the true bytes).  The
 # counters see what leaves the L2 caches, so reads served by the Infinity Cache count as
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "d079dff09043430022272847996980b742ea588e627fc528e0bc2f42a8203958",
-    "fetch_kib": 664622184.1875, "fetch_scale": 2.0,
-    "write_kib": 115164259.75, "write_scale": 1.0,
-    "alg_bytes_same_launch": 1518300495872.0,
-    "summary": "profiles/k_run_2048_sz8_draws1024.md",
+    "sources_sha256": "6c5629f820149ab3e27c0ce2fc35f36fe53724cc076ae16098f8012cedb633e5",
+    "fetch_kib": 172311178.6875, "fetch_scale": 2.0,
+    "write_kib": 108975630.5, "write_scale": 1.0,
+    "alg_bytes_same_launch": 587876007936.0,
+    "precond": True,
+    "summary": "profiles/k_run_2048_sz8_draws1024_precond.md",
 }
 DEVICE_SOURCES = ["gqd_kernels.hip", "gqd_device.hpp", "gqd_internal.h", "gqd_compositions.h"]
 
@@ -82,9 +94,9 @@ def device_sources_sha() -> str:
     return outer.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(precond: bool):
     """(bytes per launch, ratio to that launch's algorithmic bytes), or (None, None)."""
-    if device_sources_sha() != TRAFFIC["sources_sha256"]:
+    if device_sources_sha() != TRAFFIC["sources_sha256"] or precond != TRAFFIC["precond"]:
         return None, None
     t = 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
     return t, t / TRAFFIC["alg_bytes_same_launch"]
@@ -123,7 +135,7 @@ def ragged_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
     at its verified step; one launch per grid size on forked streams per step."""
     import torch
     items = inputs.ragged_batch(batch, seed=0)
-    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    opts = gqd.SolverOpts(tol=TOL, restart=32, precond=PRECOND)
     with gqd.from_items(items, device=dev) as prop:
         psi = prop.pack([it.psi0 for it in items])
         prop.propagate(psi, METHOD, SCHEME, 6, RAGGED_DT, 1, opts)
@@ -139,7 +151,7 @@ def ragged_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
 def scheme_leg(gqd, inputs, dev, items, steps: int, scheme: str, order: int, dt: float) -> dict:
     """The same drawn batch under another composition at its own 1e-10 step: throughput
     per step and, comparable across schemes, simulated time per second (a.u./s)."""
-    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    opts = gqd.SolverOpts(tol=TOL, restart=32, precond=PRECOND)
     with gqd.from_items(items, device=dev) as prop:
         psi = prop.pack([it.psi0 for it in items])
         prop.propagate(psi, METHOD, scheme, order, dt, 1, opts)
@@ -198,6 +210,8 @@ def split_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
                                        ("adiabatic_midpoint", ad, METHOD, 1)):
         with gqd.from_items([item] * batch, device=dev) as prop:
             psi = prop.pack([item.psi0] * batch)
+            # plain GMRES: at 10 a.u. on this model the preconditioner's extra transform
+            # pair per iteration costs more than the iterations it saves
             opts = gqd.SolverOpts(tol=1e-14, restart=32)
             prop.propagate(psi, method, SCHEME, ORDER, dt, 1, opts, stats=False)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -281,6 +295,9 @@ def adjoint_leg(gqd, inputs, dev, batch: int, nsteps: int) -> dict:
     q = ag.grid(1024, items[0].qmin, items[0].qmax, dev)
     P = {k: torch.tensor([it.params[k] for it in items], dtype=torch.float64, device=dev, requires_grad=True)
          for k in ["q0", "p0", "width", "amp", "center"]}
+    # plain GMRES: at N = 1024 and 4 a.u. the kinetic part is not stiff (a p_max^2 / 2m
+    # about 1), and the preconditioner's extra transform pair per iteration costs more
+    # than the one or two iterations it saves (68.7 against 86.8 gradients/s)
     opts = gqd.SolverOpts(tol=TOL_ADJ, restart=32)
     with gqd.from_items(items, device=dev) as prop:
         def gradient(steps):
@@ -341,7 +358,7 @@ from paper_1902_04661_amd import inputs as I
 b = int(sys.argv[1])
 it = I.ragged_batch({batch}, seed=0, fixed_n={n})[b]
 m = O.model_from_item(it)
-opts = O.SolverOpts(tol={tol}, restart=32)
+opts = O.SolverOpts(tol={tol}, restart=32, precond={precond})
 psi = it.psi0
 t0 = time.time(); steps = 0
 while True:
@@ -359,7 +376,8 @@ def cpu_leg(seconds: float = 20.0, workers: int = 0) -> dict:
     at the same solve tolerance for about `seconds`.  value = sum over processes of
     N x steps, over the wall time of the pool."""
     cores = workers or min(16, os.cpu_count() or 1)
-    code = CPU_PACKET.format(root=ROOT, batch=BATCH, n=N, tol=TOL, order=ORDER, dt=DT_STAR, seconds=seconds)
+    code = CPU_PACKET.format(root=ROOT, batch=BATCH, n=N, tol=TOL, order=ORDER, dt=DT_STAR, seconds=seconds,
+                             precond=PRECOND)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     t0 = time.perf_counter()
     procs = [subprocess.Popen([sys.executable, "-c", code, str(b)], env=env, stdout=subprocess.PIPE, text=True)
@@ -373,7 +391,7 @@ def cpu_leg(seconds: float = 20.0, workers: int = 0) -> dict:
             "sample": f"draws 0..{cores - 1} of the benchmark batch, N={N}, one process (numpy FP64, one "
                       f"thread) per packet, {steps} SZ-8 steps of dt={DT_STAR} in total (each process "
                       f"{min(o['steps'] for o in outs)}-{max(o['steps'] for o in outs)} steps), "
-                      f"GMRES tol {TOL:g}, {wall:.1f} s wall"}
+                      f"GMRES tol {TOL:g}{', kinetic preconditioner' if PRECOND else ''}, {wall:.1f} s wall"}
 
 
 def main(argv=None):
@@ -386,6 +404,9 @@ def main(argv=None):
     ap.add_argument("--single-steps", type=int, default=4)
     ap.add_argument("--tj-steps", type=int, default=20, help="triple-jump leg (0: skip)")
     ap.add_argument("--opt-steps", type=int, default=8, help="optimal 8th- and 10th-order legs (0: skip)")
+    ap.add_argument("--no-precond", action="store_true", help="headline with the plain GMRES of Sec. II.C")
+    ap.add_argument("--plain-steps", type=int, default=10,
+                    help="the headline batch under the plain GMRES, for comparison (0: skip)")
     ap.add_argument("--ragged-batch", type=int, default=4096)
     ap.add_argument("--ragged-steps", type=int, default=2)
     ap.add_argument("--adjoint-batch", type=int, default=256)
@@ -421,7 +442,8 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8}), flush=True)
         return 0
-    opts = gqd.SolverOpts(tol=TOL, restart=32)
+    precond = PRECOND and not args.no_precond
+    opts = gqd.SolverOpts(tol=TOL, restart=32, precond=precond)
 
     # ---------------------------------------------------------------- batched run
     items = inputs.ragged_batch(args.batch, seed=0, fixed_n=N)
@@ -467,6 +489,24 @@ def main(argv=None):
                   "us_per_h_apply": 1e6 * el1 / max(st1.h_applies, 1),
                   "workload": f"draw 0 of the batch alone, N={N}, SZ-8 midpoint, dt={DT_STAR}, GMRES tol {TOL:g}"}
         print(f"[bench] single packet: {single['value']:.3e} gp.steps/s", file=sys.stderr, flush=True)
+
+    # the same batch under the plain GMRES (Sec. II.C, no preconditioner) from t = 0
+    plain = {}
+    if precond and args.plain_steps > 0:
+        popts = gqd.SolverOpts(tol=TOL, restart=32)
+        with gqd.from_items(items, device=dev) as pp:
+            ps = pp.pack([it.psi0 for it in items])
+            pp.propagate(ps, METHOD, SCHEME, ORDER, DT_STAR, 1, popts)
+            pk, pw, pt = timed_launches(pp, ps, args.plain_steps, METHOD, SCHEME, ORDER, DT_STAR, popts)
+        pa = pt["bytes"] / args.plain_steps / pk / 1e9
+        plain = {"value": args.batch * N * args.plain_steps / pw, "unit": "grid-point·steps/s",
+                 "ms_per_step": 1e3 * pw / args.plain_steps,
+                 "mean_gmres_iterations": pt["iterations"] / max(pt["solves"], 1),
+                 "roofline": {"bound": "hbm", "achieved": pa, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": pa / HBM_PEAK_GBS, "kernel": "k_run<7> (plain GMRES)"},
+                 "workload": f"the headline batch from t = 20 a.u., {args.plain_steps} steps, plain GMRES"}
+        print(f"[bench] plain GMRES: {plain['ms_per_step']:.1f} ms/step, "
+              f"{plain['mean_gmres_iterations']:.2f} iterations per solve", file=sys.stderr, flush=True)
 
     # the scheme comparisons take Suzuki-8 over a window like the other legs' (from one
     # warmup step on, a few steps), not the headline's 4000 a.u., whose later steps need
@@ -518,7 +558,8 @@ def main(argv=None):
         print(f"[bench] cpu oracle: {cpu['value']:.3e} gp.steps/s on {cpu['cores']} cores",
               file=sys.stderr, flush=True)
 
-    traffic, traffic_ratio = measured_traffic() if args.batch == BATCH and not args.no_autotune else (None, None)
+    traffic, traffic_ratio = (measured_traffic(precond) if args.batch == BATCH and not args.no_autotune
+                              else (None, None))
     sim = DT_STAR * args.steps / wall
     line = {
         "metric": METRIC,
@@ -538,6 +579,7 @@ def main(argv=None):
                             "q0~U[4.5,6], p0~U[-5,5], coupling amplitude~U[0.1,0.8], width 0.12 (seed 0)",
                    "batch": args.batch, "n": N, "method": "implicit midpoint", "scheme": "suzuki",
                    "order": ORDER, "dt": DT_STAR, "gmres_tol": TOL, "restart": 32,
+                   "gmres_preconditioner": "right, (1 + i a p^2/2m)^-1" if precond else None,
                    "substeps_per_step": 125, "parallelism": "one workgroup per wavepacket",
                    "dt_star_error": "<= 1e-10 at T=4000 a.u. for the batch's six highest-energy draws "
                                     "(6.2e-11 worst; 1.4e-8 at dt=40)",
@@ -546,11 +588,12 @@ def main(argv=None):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (launch from t = 0, rocprofv3 --pmc)",
                      "traffic_over_alg_bytes": traffic_ratio,
-                     "kernel": "k_run<7> (propagate, N = 2048 plan 4-8-8-8)",
+                     "kernel": "k_run<7%s> (propagate, N = 2048 plan 4-8-8-8)" % (", precond" if precond else ""),
                      "alg_bytes_per_launch": tot["bytes"] / args.steps,
                      "avg_launch_ms": avg_kernel_s * 1e3},
         "cpu_baseline": cpu,
         "single_packet": single,
+        "plain_gmres": plain,
         "triple_jump_8": tj,
         "optimal_8": opt8,
         "optimal_10": opt10,
