@@ -251,17 +251,19 @@ def cost_at(errors: Sequence[float], costs: Sequence[float], target: float, orde
 
 
 def efficiency(item, T: float = 4000.0, cases=EFFICIENCY_CASES, method: str = "trap",
-               ref=("optimal", 10, 1.25), tol: float = 1e-17, restart: int = 48, log=print) -> dict:
+               ref=("optimal", 10, 1.25), tol: float = 1e-17, restart: int = 48, precond: bool = False,
+               log=print) -> dict:
     """Convergence error against GPU time per scheme (Sec. III, Fig. 6): every run is one
     packet alone, its error the grid L2 distance at T to the reference run (by default
     the optimal tenth-order composition at 1.25 a.u., as the paper takes its finest
     optimal tenth-order run), its cost the GPU time of its launches and its count of H
-    applications.  Costs at errors 1e-5 and 1e-10 by cost_at()."""
-    opts = gqd.SolverOpts(tol=tol, restart=restart, maxit=4000)
+    applications.  Costs at errors 1e-5 and 1e-10 by cost_at().  precond: every solve
+    right-preconditioned by the kinetic inverse."""
+    opts = gqd.SolverOpts(tol=tol, restart=restart, maxit=4000, precond=precond)
     t0 = time.time()
     ref_state, ref_s, _ = timed_run(item, method, ref[0], ref[1], ref[2], T, opts)
     log(f"  reference {ref[0]}-{ref[1]} dt {ref[2]}: {ref_s:.1f} s GPU")
-    out = {"T": T, "n": item.n, "method": method, "tol": tol, "reference": list(ref),
+    out = {"T": T, "n": item.n, "method": method, "tol": tol, "precond": precond, "reference": list(ref),
            "packet": dict(item.params), "cases": []}
     for scheme, order, dts in cases:
         rec = {"scheme": scheme, "order": order, "dt": list(dts), "error": [], "gpu_s": [], "h_applies": [],
@@ -303,6 +305,7 @@ def main(argv=None):
     ap.add_argument("--draws", type=int, default=-1,
                     help="packet set: the resting and moving packets plus this many fastest draws "
                          "(order 8, Suzuki and triple jump)")
+    ap.add_argument("--precond", action="store_true", help="efficiency study with the kinetic preconditioner")
     ap.add_argument("--extra", nargs="*", default=[],
                     help="packet set: more schemes as scheme:order:k_first:k_last (dt = dt0 2^-k)")
     ap.add_argument("--efficiency", action="store_true",
@@ -315,7 +318,7 @@ def main(argv=None):
         d = inputs.ragged_batch_draws(1024, 0)
         b = int(hardest_draws(d, 1)[0])
         item = inputs.nai_like_item(args.n, q0=float(d["q0"][b]), p0=float(d["p0"][b]), amp=float(d["amp"][b]))
-        res = efficiency(item, args.T, tol=args.tol, log=log)
+        res = efficiency(item, args.T, tol=args.tol, precond=args.precond, log=log)
     elif args.draws >= 0:
         extra = [(e.split(":")[0], int(e.split(":")[1]), (int(e.split(":")[2]), int(e.split(":")[3])))
                  for e in args.extra]
