@@ -74,3 +74,21 @@ def test_invalid_arguments_fail_without_a_gpu():
     m2 = (ctypes.c_double * 2)(1.0, -1.0)
     desc = gqd._GridDesc(2, 2, 1, n2, q0, q1, m2)
     assert lib.gqd_create(ctypes.byref(h), ctypes.byref(desc)) == -1   # mass of the second axis
+
+
+def header_struct_fields(name):
+    """Member names, in order, of `typedef struct { ... } name;` in the header."""
+    text = open(HEADER).read()
+    end = re.search(r"\}\s*" + name + r";", text)
+    assert end, name
+    start = text.rfind("typedef struct {", 0, end.start())
+    body = re.sub(r"/\*.*?\*/", "", text[start + len("typedef struct {"):end.start()], flags=re.S)
+    return re.findall(r"(\w+)\s*;", body)
+
+
+@pytest.mark.parametrize("cname,pyname", [("gqd_solver_opts", "_SolverOpts"), ("gqd_stats", "_Stats"),
+                                          ("gqd_grid_desc", "_GridDesc")])
+def test_binding_structs_mirror_the_header(cname, pyname):
+    from paper_1902_04661_amd import gqd
+    fields = [f[0] for f in getattr(gqd, pyname)._fields_]
+    assert fields == header_struct_fields(cname)
