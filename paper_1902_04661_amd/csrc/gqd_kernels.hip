@@ -575,6 +575,148 @@ struct Eng {
       }
     }
   }
+  // wfused with two results from one forward transform: dst gets the inverse's first
+  // pass of M^-1 X and dst2 that of p M^-1 X, M = 1 + i ktau p^2 (the preconditioner and
+  // the momentum of its result, for the fused first turn of a preconditioned Arnoldi
+  // step).  dst2 is the wave's own region of the other buffer.
+  template <int TP, bool SWIN>
+  static __device__ __forceinline__ void wfused2(const GQD_L cplx* src, GQD_L cplx* dst, GQD_L cplx* dst2,
+                                                 const Ctx& c, int slab0, double ktau) {
+    constexpr int NR = M / RF;
+    constexpr int NB = SPW * NR;
+    static_assert(NB % 64 == 0, "whole butterflies per lane");
+    constexpr int PER = NB / 64;
+    cplx x[PER][RF], z[PER][RF];
+    {
+      const int l = lane_tid() & 63;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int b = l + 64 * q, e = b / NR, j = b % NR;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+          const int i = e * M + j + r * NR;
+          x[q][r] = src[SWIN ? swz(i) : i];
+        }
+      }
+    }
+    {
+      const GQD_G cplx* tw = opaque(c.tw) + pass_table_offset(PLAN, TP);
+      const int l = lane_tid() & 63;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int j = (l + 64 * q) % NR;
+#pragma unroll
+        for (int r = 1; r < RF; ++r) x[q][r] = cmul(x[q][r], tw[j * (RF - 1) + r - 1]);
+      }
+    }
+    const double scale = opaque_d(c.pscale) / (double)N;
+    {
+      const int l = lane_tid() & 63;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int b = l + 64 * q, e = b / NR, j = b % NR;
+        const int k1 = (slab0 + e) % R0;
+        DFT<RF, -1>::run(x[q]);
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+          const int kk = k1 + R0 * (j + r * NR);          // k-space index
+          const int kp = (kk < N / 2) ? kk : kk - N;      // signed wavenumber
+          // (1 + i ktau p^2)^-1 / N = (1 - i q) / (N (1 + q^2)), q = ktau p^2; times p
+          const double pk = scale * (double)N * (double)kp;
+          const double qk = ktau * pk * pk;
+          const double inv = 1.0 / ((double)N * (1.0 + qk * qk));
+          x[q][r] = mk((x[q][r].x + qk * x[q][r].y) * inv, (x[q][r].y - qk * x[q][r].x) * inv);
+          z[q][r] = cscale(x[q][r], pk);
+        }
+        DFT<RF, +1>::run(x[q]);
+        DFT<RF, +1>::run(z[q]);
+      }
+    }
+    {
+      const int l = lane_tid() & 63;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int b = l + 64 * q, e = b / NR, j = b % NR;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+          dst[swz(e * M + j * RF + r)] = x[q][r];
+          dst2[swz(e * M + j * RF + r)] = z[q][r];
+        }
+      }
+    }
+  }
+  // uz = M^-1 x and upz = p M^-1 x, M = 1 + i ktau p^2, from one forward transform
+  // (four-step, two-buffer plans): the forward exchange goes through b0 and the slab
+  // passes run in b1 as in kinetic_fs; the fused pass leaves M^-1 X in b1 and p M^-1 X in
+  // the wave's region of b0, the inverse passes run on both, and both return through
+  // the exchange.  x is read before uz or upz is written, so either may alias it.
+  static __device__ void kinetic_fs_mz(const OV& x, OV& uz, OV& upz, const Ctx& c, double ktau) {
+    static_assert(kFS && kPP, "two results need the two-buffer four-step form");
+    GQD_L cplx* b0 = c.fft;
+    GQD_L cplx* b1 = c.fft + 2 * N;
+    cplx wo[R0 - 1];
+    {
+      const GQD_G cplx* tk = opaque(c.tw) + pass_table_offset(PLAN, 0) + lane_tid() * (R0 - 1);
+#pragma unroll
+      for (int k1 = 1; k1 < R0; ++k1) wo[k1 - 1] = tk[k1 - 1];
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      cplx y[R0];
+#pragma unroll
+      for (int r = 0; r < R0; ++r) y[r] = x.v[s][r];
+      DFT<R0, -1>::run(y);
+#pragma unroll
+      for (int k1 = 1; k1 < R0; ++k1) y[k1] = cmul(y[k1], wo[k1 - 1]);
+      const int t = lane_tid();
+#pragma unroll
+      for (int k1 = 0; k1 < R0; ++k1) b0[(s * R0 + k1) * M + t] = y[k1];
+    }
+    __syncthreads();
+    const int slab0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * SPW;
+    GQD_L cplx* X = b0 + slab0 * M;
+    GQD_L cplx* Y = b1 + slab0 * M;
+    if constexpr (R3 == 1) {
+      wpass<R1, 1, -1, -1, false, true, false>(X, Y, c, slab0);
+      wave_sync();
+      wfused2<1, true>(Y, Y, X, c, slab0, ktau);
+      wave_sync();
+      wpass<R1, R2, +1, 2, true, false, true>(Y, Y, c, slab0);
+      wpass<R1, R2, +1, 2, true, false, true>(X, X, c, slab0);
+    } else {
+      wpass<R1, 1, -1, -1, false, true, false>(X, Y, c, slab0);
+      wave_sync();
+      wpass<R2, R1, -1, 1, true, false, false>(Y, Y, c, slab0);
+      wave_sync();
+      wfused2<2, false>(Y, Y, X, c, slab0, ktau);
+      wave_sync();
+      wpass<R2, R3, +1, 3, true, false, false>(Y, Y, c, slab0);
+      wpass<R2, R3, +1, 3, true, false, false>(X, X, c, slab0);
+      wave_sync();
+      wpass<R1, R3 * R2, +1, 4, false, false, true>(Y, Y, c, slab0);
+      wpass<R1, R3 * R2, +1, 4, false, false, true>(X, X, c, slab0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      cplx y[R0], w[R0];
+      const int t = lane_tid();
+#pragma unroll
+      for (int q = 0; q < R0; ++q) {
+        y[q] = b1[(s * R0 + q) * M + t];
+        w[q] = b0[(s * R0 + q) * M + t];
+      }
+      DFT<R0, +1>::run(y);
+      DFT<R0, +1>::run(w);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        uz.v[s][r] = y[r];
+        upz.v[s][r] = w[r];
+      }
+    }
+    __syncthreads();  // b0 was read above; the next application's exchange writes it
+  }
+
   template <int KM = 0>
   static __device__ void kinetic_fs(const OV& x, OV& u, const Ctx& c, double ktau) {
     GQD_L cplx* b0 = c.fft;                          // forward exchange
@@ -940,7 +1082,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
 
   // operator request: H - opshift applied to opsrc (opshift = 0 outside Arnoldi), or
   // (opK) the preconditioner (1 + i ktau p^2)^-1, one transform pair, no coupling
-  bool pending = false, opH = false, op_in_y = false, opK = false;
+  bool pending = false, opH = false, op_in_y = false, opK = false, opKH = false;
   double opktau = 0.0;
   bool prec_cv = false;  // preconditioned cycle: converged by the estimate
   bool psi_in_y = false;  // y holds psi at owned points (set by the midpoint update)
@@ -976,7 +1118,15 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
     opshift = shift;
     op_in_y = in_y;
     opK = false;
+    opKH = false;
     half = 0;
+  };
+  // H M^-1 on y (two-buffer four-step plans): the first turn makes z = M^-1 y (stored to
+  // S3) and A z from one forward transform, the second turn A A z as usual
+  auto request_prec_h = [&]() {
+    request(nullptr, true, 0.0, true);
+    opKH = true;
+    opktau = al * a.inv2m;
   };
   // the preconditioner M^-1 = (1 + i al p^2 / 2m)^-1 of the current solve on y
   auto request_prec = [&]() {
@@ -986,6 +1136,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
     opshift = 0.0;
     op_in_y = true;
     opK = true;
+    opKH = false;
     opktau = al * a.inv2m;
     half = 0;
   };
@@ -1056,7 +1207,18 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
       } else {
         t = y;
       }
-      E::kinetic(t, y, c);
+      if constexpr (PC && E::kFS && E::kPP) {
+        if (half == 0 && opKH) {
+          // preconditioned Arnoldi step: z = M^-1 v and p z from one forward transform;
+          // z becomes the operand of H (kept for the second turn and in S3 for w)
+          E::kinetic_fs_mz(t, keep, y, c, opktau);
+          E::store(keep, S3);
+        } else {
+          E::kinetic(t, y, c);
+        }
+      } else {
+        E::kinetic(t, y, c);
+      }
       if (half == 0) {
         if constexpr (E::kPP) {
           E::couple(y, keep, c);
@@ -1222,8 +1384,13 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         // (the next block reduction's barrier orders this write before any read)
         j = 0;
         if constexpr (PC) {
-          request_prec();
-          pc = kPrecZ;
+          if constexpr (E::kFS && E::kPP) {
+            request_prec_h();
+            pc = kPrecArnoldi;
+          } else {
+            request_prec();
+            pc = kPrecZ;
+          }
           break;
         }
         request(basis, true, kind_mu ? sig1 : sig0, true);
@@ -1288,8 +1455,13 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
               for (int r = 0; r < R0; ++r) y.v[s][r] = cscale(y.v[s][r], sc);
             ++j;
             E::store(y, basis + (size_t)j * E::VEC);
-            request_prec();
-            pc = kPrecZ;
+            if constexpr (E::kFS && E::kPP) {
+              request_prec_h();
+              pc = kPrecArnoldi;
+            } else {
+              request_prec();
+              pc = kPrecZ;
+            }
             break;
           }
           // cycle ends: x += M^-1 (V y) over the k = j + 1 basis vectors
