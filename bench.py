@@ -74,10 +74,10 @@ TOL_ADJ = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "6c5629f820149ab3e27c0ce2fc35f36fe53724cc076ae16098f8012cedb633e5",
-    "fetch_kib": 172311178.6875, "fetch_scale": 2.0,
-    "write_kib": 108975630.5, "write_scale": 1.0,
-    "alg_bytes_same_launch": 587876007936.0,
+    "sources_sha256": "6faed316a76906a4864b4e449d83e3aba2d981cdf96896f0d833288359238e57",
+    "fetch_kib": 186599898.75, "fetch_scale": 2.0,
+    "write_kib": 108989711.625, "write_scale": 1.0,
+    "alg_bytes_same_launch": 587693031424.0,
     "precond": True,
     "summary": "profiles/k_run_2048_sz8_draws1024_precond.md",
 }
