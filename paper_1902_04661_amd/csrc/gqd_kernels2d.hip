@@ -32,9 +32,6 @@ struct G2 {
   static constexpr int NPTS = NL * NL;
   static constexpr long long VEC = 2LL * NPTS;
   static constexpr int NBA = NL / WV;  // line blocks per axis
-  static constexpr int LOG2 = NL == 64 ? 6 : NL == 128 ? 7 : NL == 256 ? 8 : 9;
-  static constexpr int N4 = LOG2 / 2;      // radix-4 passes per transform
-  static constexpr bool ODD = LOG2 & 1;    // one radix-2 pass at the end
   static_assert(NL % 64 == 0 && NL >= 64 && NL <= 512, "line length");
 };
 
@@ -183,12 +180,43 @@ __device__ bool grid_sum(const Ctx2& c, GridSync& s, double* part, int& par, int
 }
 
 // ------------------------------------------------------------ line transforms
+// Line transform plans: radices (L1, L2, L3) with L1 L2 L3 = NL (L3 = 1: two factors).
+// The forward transform runs Stockham passes of L1 (and L2), the last forward pass, the
+// multiply by p_k / NL and the first inverse pass run as one fused pass, then the
+// inverse passes of the remaining radices in reverse order: 3 passes at NL = 64 and 5
+// from 128 to 512, each one read and one write of the line through LDS.
+template <int NL>
+struct LinePlan;
+template <>
+struct LinePlan<64> {
+  static constexpr int L1 = 8, L2 = 8, L3 = 1;
+};
+template <>
+struct LinePlan<128> {
+  static constexpr int L1 = 4, L2 = 4, L3 = 8;
+};
+template <>
+struct LinePlan<256> {
+  static constexpr int L1 = 4, L2 = 8, L3 = 8;
+};
+template <>
+struct LinePlan<512> {
+  static constexpr int L1 = 8, L2 = 8, L3 = 8;
+};
+
+// LDS slot of line element i in a swizzled buffer: bits 3-5 are XORed into the low
+// three bits.  The passes with Ns = 1 give each lane a run of R consecutive outputs,
+// which unswizzled would put eight lanes of a 16-byte store on the same banks; those
+// outputs are stored, and read by the next pass, through this map.
+__device__ __forceinline__ int lswz(int i) { return i ^ ((i >> 3) & 7); }
+
 // One Stockham pass of radix R (sub-transform size Ns) over both surfaces of the
-// wave's line; S = -1 forward, +1 inverse.  With PMUL the inputs are first
-// multiplied by p_k / NL (the k-space factor of p, and the inverse's 1/NL).
-template <int NL, int R, int S, bool PMUL>
-__device__ __forceinline__ void line_pass(const GQD_L cplx* src, GQD_L cplx* dst, int Ns, const Ctx2& c,
-                                          double pn) {
+// wave's line; S = -1 forward, +1 inverse.  Butterfly j of surface s reads
+// x[j + r NL/R], twiddles by w_{R Ns}^{r k} (k = j mod Ns) from the line table and
+// writes y[(j - k) R + k + r Ns].  SWIN / SWOUT route the input / output index
+// through lswz.
+template <int NL, int R, int S, bool SWIN, bool SWOUT>
+__device__ __forceinline__ void line_pass(const GQD_L cplx* src, GQD_L cplx* dst, int Ns, const Ctx2& c) {
   constexpr int NR = NL / R;
   constexpr int NB = 2 * NR;
   const int lane = threadIdx.x & 63;
@@ -204,8 +232,7 @@ __device__ __forceinline__ void line_pass(const GQD_L cplx* src, GQD_L cplx* dst
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = j + r * NR;
-        v[r] = in[idx];
-        if constexpr (PMUL) v[r] = cscale(v[r], pn * (double)(idx < NL / 2 ? idx : idx - NL));
+        v[r] = in[SWIN ? lswz(idx) : idx];
       }
       const int step = NL / (R * Ns);
 #pragma unroll
@@ -217,7 +244,47 @@ __device__ __forceinline__ void line_pass(const GQD_L cplx* src, GQD_L cplx* dst
       DFT<R, S>::run(v);
       const int o = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) out[o + r * Ns] = v[r];
+      for (int r = 0; r < R; ++r) {
+        const int idx = o + r * Ns;
+        out[SWOUT ? lswz(idx) : idx] = v[r];
+      }
+    }
+  }
+}
+
+// Last forward pass (radix R, Ns = NL/R), momentum multiply and first inverse pass
+// (radix R, Ns = 1) in registers: butterfly j's forward outputs are the k-space points
+// j + r NL/R, which are exactly the inputs of inverse butterfly j.  The inverse pass
+// writes y[j R + r] through lswz.
+template <int NL, int R, bool SWIN>
+__device__ __forceinline__ void line_fused(const GQD_L cplx* src, GQD_L cplx* dst, const Ctx2& c, double pn) {
+  constexpr int NR = NL / R;
+  constexpr int NB = 2 * NR;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int b0 = 0; b0 < NB; b0 += 64) {
+    const int bb = b0 + lane;
+    if (NB % 64 == 0 || bb < NB) {
+      const int s = bb / NR, j = bb % NR;
+      const GQD_L cplx* in = src + s * NL;
+      GQD_L cplx* out = dst + s * NL;
+      cplx v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int idx = j + r * NR;
+        v[r] = in[SWIN ? lswz(idx) : idx];
+      }
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], c.tw[r * j]);
+      DFT<R, -1>::run(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int kk = j + r * NR;  // k-space index
+        v[r] = cscale(v[r], pn * (double)(kk < NL / 2 ? kk : kk - NL));
+      }
+      DFT<R, 1>::run(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) out[lswz(j * R + r)] = v[r];
     }
   }
 }
@@ -226,6 +293,7 @@ __device__ __forceinline__ void line_pass(const GQD_L cplx* src, GQD_L cplx* dst
 template <int NL>
 __device__ void line_kinetic(const cplx (&x)[2][NL / 64], cplx (&y)[2][NL / 64], const Ctx2& c, double ps) {
   using E = G2<NL>;
+  using L = LinePlan<NL>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   GQD_L cplx* b0 = c.lines + (size_t)wave * 4 * NL;
   GQD_L cplx* b1 = b0 + 2 * NL;
@@ -234,48 +302,33 @@ __device__ void line_kinetic(const cplx (&x)[2][NL / 64], cplx (&y)[2][NL / 64],
 #pragma unroll
     for (int r = 0; r < E::P; ++r) b0[s * NL + lane + 64 * r] = x[s][r];
   __syncthreads();
-  GQD_L cplx* src = b0;
-  GQD_L cplx* dst = b1;
-  int Ns = 1;
-#pragma unroll
-  for (int p = 0; p < E::N4; ++p) {
-    line_pass<NL, 4, -1, false>(src, dst, Ns, c, 0.0);
-    __syncthreads();
-    GQD_L cplx* t = src;
-    src = dst;
-    dst = t;
-    Ns *= 4;
-  }
-  if constexpr (E::ODD) {
-    line_pass<NL, 2, -1, false>(src, dst, Ns, c, 0.0);
-    __syncthreads();
-    GQD_L cplx* t = src;
-    src = dst;
-    dst = t;
-  }
   const double pn = ps / (double)NL;
-  Ns = 1;
-#pragma unroll
-  for (int p = 0; p < E::N4; ++p) {
-    if (p == 0)
-      line_pass<NL, 4, 1, true>(src, dst, Ns, c, pn);
-    else
-      line_pass<NL, 4, 1, false>(src, dst, Ns, c, 0.0);
+  GQD_L cplx* out;
+  if constexpr (L::L3 == 1) {
+    line_pass<NL, L::L1, -1, false, true>(b0, b1, 1, c);
     __syncthreads();
-    GQD_L cplx* t = src;
-    src = dst;
-    dst = t;
-    Ns *= 4;
-  }
-  if constexpr (E::ODD) {
-    line_pass<NL, 2, 1, false>(src, dst, Ns, c, 0.0);
+    line_fused<NL, L::L2, true>(b1, b0, c, pn);
     __syncthreads();
-    src = dst;
+    line_pass<NL, L::L1, 1, true, false>(b0, b1, L::L2, c);
+    __syncthreads();
+    out = b1;
+  } else {
+    line_pass<NL, L::L1, -1, false, true>(b0, b1, 1, c);
+    __syncthreads();
+    line_pass<NL, L::L2, -1, true, false>(b1, b0, L::L1, c);
+    __syncthreads();
+    line_fused<NL, L::L3, false>(b0, b1, c, pn);
+    __syncthreads();
+    line_pass<NL, L::L2, 1, true, false>(b1, b0, L::L3, c);
+    __syncthreads();
+    line_pass<NL, L::L1, 1, false, false>(b0, b1, L::L3 * L::L2, c);
+    __syncthreads();
+    out = b1;
   }
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int r = 0; r < E::P; ++r) y[s][r] = src[s * NL + lane + 64 * r];
+    for (int r = 0; r < E::P; ++r) y[s][r] = out[s * NL + lane + 64 * r];
   __syncthreads();
 }
 
