@@ -243,6 +243,7 @@ def twod_leg(gqd, inputs, dev, steps: int) -> dict:
         e0.record(s)
         st = prop.propagate(psi, METHOD, SCHEME, ORDER, DT_2D, steps, opts)
         e1.record(s)
+        torch.cuda.synchronize()
         el = time.perf_counter() - t0
         kern = e0.elapsed_time(e1) * 1e-3
     gbs = st.alg_bytes / kern / 1e9

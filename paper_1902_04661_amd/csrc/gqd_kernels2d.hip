@@ -168,11 +168,30 @@ __device__ bool grid_sum(const Ctx2& c, GridSync& s, double* part, int& par, int
   if (!grid_barrier(s, c.scal + 15)) return false;
   const double* all = part + (size_t)par * s.G * kPart2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int k = wave; k < K; k += kLineWaves) {
-    double t = 0.0;
-    for (int gg = lane; gg < s.G; gg += 64) t += all[(size_t)gg * kPart2 + k];
-    t = wave_sum(t);
-    if (lane == 0) c.red[k] = t;
+  // wave w sums slots w, w + WV, ...; the loads of four of its slots are issued before
+  // any is added (G <= 256: at most four partials per lane and slot), and each slot is
+  // summed over the workgroups in increasing order
+  for (int kb = wave; kb < K; kb += 4 * kLineWaves) {
+    double v[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = kb + q * kLineWaves;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gg = lane + 64 * r;
+        v[q][r] = (k < K && gg < s.G) ? all[(size_t)gg * kPart2 + k] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (lane + 64 * r < s.G) t += v[q][r];
+      t = wave_sum(t);
+      const int k = kb + q * kLineWaves;
+      if (lane == 0 && k < K) c.red[k] = t;
+    }
   }
   __syncthreads();
   par ^= 1;
@@ -410,25 +429,53 @@ __device__ void line_op(const LineReq& q, const Ctx2& c, const K2Args& a, const 
         block_map<NL>(row, threadIdx.x + (e0 + u) * kThreads2, s, w, i);
         gi[u] = line_gidx<NL>(row, s, l0 + w, i);
         li[u] = w * 4 * NL + s * NL + i;
-        v[u] = q.src[gi[u]];
       }
+      // all sources are requested before any is used (after a grid barrier every read
+      // misses the L2, so each round of dependent loads costs a full memory latency)
+      cplx t2[EB], t3[EB];
+#pragma unroll
+      for (int u = 0; u < EB; ++u) v[u] = q.src[gi[u]];
       if (q.src2) {
 #pragma unroll
         for (int u = 0; u < EB; ++u) t[u] = q.src2[gi[u]];
+      }
+      if (q.h1) {
+#pragma unroll
+        for (int u = 0; u < EB; ++u) t2[u] = q.h1[gi[u]];
+      }
+      if (q.h2) {
+#pragma unroll
+        for (int u = 0; u < EB; ++u) t3[u] = q.h2[gi[u]];
+      }
+      if (q.src2) {
 #pragma unroll
         for (int u = 0; u < EB; ++u) v[u] = cadd(v[u], t[u]);
       }
       if (q.h1) {
-#pragma unroll
-        for (int u = 0; u < EB; ++u) t[u] = q.h1[gi[u]];
         if (q.h2) {
 #pragma unroll
-          for (int u = 0; u < EB; ++u) t[u] = cadd(t[u], q.h2[gi[u]]);
+          for (int u = 0; u < EB; ++u) t2[u] = cadd(t2[u], t3[u]);
         }
 #pragma unroll
-        for (int u = 0; u < EB; ++u) v[u] = csub(v[u], cmul_is(t[u], q.hal));
+        for (int u = 0; u < EB; ++u) v[u] = csub(v[u], cmul_is(t2[u], q.hal));
       }
-      for (int k = 0; k < q.K; ++k) {
+      // basis vectors two at a time, both loads in flight together
+      int k = 0;
+      for (; k + 1 < q.K; k += 2) {
+        const cplx* bk = q.basis + (size_t)k * E::VEC;
+        const cplx* bk1 = bk + E::VEC;
+        const cplx ck = c.coef[k], ck1 = c.coef[k + 1];
+#pragma unroll
+        for (int u = 0; u < EB; ++u) {
+          t[u] = bk[gi[u]];
+          t2[u] = bk1[gi[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < EB; ++u) v[u] = csub(v[u], cmul(ck, t[u]));
+#pragma unroll
+        for (int u = 0; u < EB; ++u) v[u] = csub(v[u], cmul(ck1, t2[u]));
+      }
+      if (k < q.K) {
         const cplx* bk = q.basis + (size_t)k * E::VEC;
         const cplx ck = c.coef[k];
 #pragma unroll
@@ -697,16 +744,38 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
     for (int i0 = 0; i0 < K; i0 += 4) {
       const int nv = K - i0 < 4 ? K - i0 : 4;
       double sx[4] = {0.0, 0.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, 0.0, 0.0};
-      for (long long e = e0 + threadIdx.x; e < e1; e += T) {
-        const cplx w = y2 ? cadd(y1[e], y2[e]) : y1[e];
-        if (i0 == 0) nn += cabs2(w);
+      // kChunkB elements per thread at a time, all their loads issued before any use
+      for (long long eb = e0 + threadIdx.x; eb < e1; eb += kChunkB * T) {
+        cplx w[kChunkB], w2[kChunkB], bv[4][kChunkB];
+#pragma unroll
+        for (int q = 0; q < kChunkB; ++q) {
+          const long long e = eb + q * T;
+          w[q] = e < e1 ? y1[e] : mk(0.0, 0.0);
+          if (y2) w2[q] = e < e1 ? y2[e] : mk(0.0, 0.0);
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
           if (u < nv) {
-            const cplx z = cconjmul(basis[(size_t)(i0 + u) * E::VEC + e], w);
-            sx[u] += z.x;
-            sv[u] += z.y;
+            const cplx* bu = basis + (size_t)(i0 + u) * E::VEC;
+#pragma unroll
+            for (int q = 0; q < kChunkB; ++q) {
+              const long long e = eb + q * T;
+              bv[u][q] = e < e1 ? bu[e] : mk(0.0, 0.0);
+            }
           }
+#pragma unroll
+        for (int q = 0; q < kChunkB; ++q) {
+          if (eb + q * T >= e1) break;
+          if (y2) w[q] = cadd(w[q], w2[q]);
+          if (i0 == 0) nn += cabs2(w[q]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (u < nv) {
+              const cplx z = cconjmul(bv[u][q], w[q]);
+              sx[u] += z.x;
+              sv[u] += z.y;
+            }
+        }
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -823,12 +892,26 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
       }
       case k2SolveResid: {
         double acc = 0.0, accb = 0.0;
-        for (long long e = e0 + threadIdx.x; e < e1; e += T) {
-          const cplx bv = bg[e];
-          const cplx r = csub(bv, cadd(xg[e], cmul_is(cadd(OR[e], OC[e]), al)));  // b - X x
-          W[e] = r;
-          acc += cabs2(r);
-          accb += cabs2(bv);
+        for (long long eb = e0 + threadIdx.x; eb < e1; eb += kChunkB * T) {
+          cplx bv[kChunkB], xv[kChunkB], o1[kChunkB], o2[kChunkB];
+#pragma unroll
+          for (int q = 0; q < kChunkB; ++q) {
+            const long long e = eb + q * T;
+            const bool in = e < e1;
+            bv[q] = in ? bg[e] : mk(0.0, 0.0);
+            xv[q] = in ? xg[e] : mk(0.0, 0.0);
+            o1[q] = in ? OR[e] : mk(0.0, 0.0);
+            o2[q] = in ? OC[e] : mk(0.0, 0.0);
+          }
+#pragma unroll
+          for (int q = 0; q < kChunkB; ++q) {
+            const long long e = eb + q * T;
+            if (e >= e1) break;
+            const cplx r = csub(bv[q], cadd(xv[q], cmul_is(cadd(o1[q], o2[q]), al)));  // b - X x
+            W[e] = r;
+            acc += cabs2(r);
+            accb += cabs2(bv[q]);
+          }
         }
         put_partial(c, 0, acc);
         put_partial(c, 1, accb);
