@@ -41,6 +41,8 @@ int class_of(int n) {
 }
 
 constexpr size_t kLdsMax = 160 * 1024;
+// a T_max above which an automatic call preconditions a size class (resolve_precond)
+constexpr double kPrecondStiffness = 2.0;
 
 }  // namespace
 
@@ -60,6 +62,9 @@ struct gqd_handle {
   int resident_cap = 0;  // workgroups the partial and sync areas are sized for
   int stats_roles = 1;   // groups per item of the last 2D launch (2: merge their statistics)
   int stats_precond = 0; // the last launch's solves were preconditioned (byte count)
+  // precond = 2 (automatic): the choice of each size class for the current call
+  bool precond_auto = false;
+  int class_precond[kNumClasses] = {};
   int spin_limit = 0;    // polls of a 2D grid wait before it gives up (0: the default)
   std::vector<ItemMeta> items;
   long long total_complex = 0;
@@ -91,9 +96,9 @@ gqd_status check_opts(const gqd_handle* h, const gqd_solver_opts* o) {
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(GQD_ERR_INVALID, "tol must be finite and > 0");
   if (o->restart < 1 || o->restart > kMaxRestart) return fail(GQD_ERR_INVALID, "restart must be in 1..64");
   if (o->maxit < 1) return fail(GQD_ERR_INVALID, "maxit must be >= 1");
-  if (o->precond != 0 && o->precond != 1) return fail(GQD_ERR_INVALID, "precond must be 0 or 1");
+  if (o->precond < 0 || o->precond > 2) return fail(GQD_ERR_INVALID, "precond must be 0, 1 or 2");
   if (h->dims == 2) {
-    if (o->precond) return fail(GQD_ERR_UNSUPPORTED, "the kinetic preconditioner is available on 1D grids");
+    if (o->precond == 1) return fail(GQD_ERR_UNSUPPORTED, "the kinetic preconditioner is available on 1D grids");
     if (lds_bytes2(h->n2, o->restart) > kLdsMax)
       return fail(GQD_ERR_UNSUPPORTED, "restart " + std::to_string(o->restart) +
                                            " needs more than 160 KB of LDS at n = " + std::to_string(h->n2) +
@@ -217,6 +222,7 @@ gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
       a.list = h->d_lists[c];
       a.nlist = (int)h->class_lists[c].size();
       a.tw = h->d_tw + h->tw_off[h->plan[c]];
+      if (h->precond_auto) a.sc.precond = h->class_precond[c];
       GQD_HIP(fn(h->plan[c], a, stream));
     }
     return GQD_OK;
@@ -232,6 +238,7 @@ gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
     a.list = h->d_lists[c];
     a.nlist = (int)h->class_lists[c].size();
     a.tw = h->d_tw + h->tw_off[h->plan[c]];
+    if (h->precond_auto) a.sc.precond = h->class_precond[c];
     GQD_HIP(fn(h->plan[c], a, h->side[c]));
     GQD_HIP(hipEventRecord(h->ev_join[c], h->side[c]));
     GQD_HIP(hipStreamWaitEvent(stream, h->ev_join[c], 0));
@@ -286,6 +293,53 @@ gqd_status make_gammas(gqd_scheme s, int order, GammaTab* gt) {
     gt->count *= gt->arity;
   }
   return GQD_OK;
+}
+
+// Largest |tau_c| of a composition's substeps (tau_c dt is the substep).
+double max_abs_tau(const GammaTab& gt) {
+  if (gt.flat) {
+    static const double flat[kFlatTauLen] = {GQD_FLAT_TAU_VALUES};
+    double t = 0.0;
+    for (int c = 0; c < gt.count; ++c) t = std::max(t, std::fabs(flat[gt.flat - 1 + c]));
+    return t;
+  }
+  double t = 1.0;
+  for (int l = 0; l < gt.levels; ++l) t *= std::max(std::fabs(gt.side[l]), std::fabs(gt.mid[l]));
+  return t;
+}
+
+// Solver option precond (0 off, 1 on, 2 automatic) resolved for one call; returns the
+// flag the launch arguments carry (for automatic calls, each size class then takes its
+// own from class_precond).  The kinetic part sets the stiffness of 1 + i a H: with
+// T_max = (pi / dq)^2 / 2m the largest kinetic energy of a class's grids and a the
+// largest half-substep, a T_max is the largest eigenvalue of a T.  The preconditioner
+// removes it at the price of one more transform pair per iteration, which pays once
+// a T_max exceeds about 2 (per-class timings of the ragged batch at Suzuki-6, 2.5 a.u.:
+// the plain solver is faster up to a T_max = 0.4 and even at 1.4, the preconditioned
+// one twice as fast at 5.7; the 8th-order batch at 20 a.u., a T_max = 5.0, 1.8x).
+// With per-item steps (not read back from the device) an automatic call
+// preconditions every class.
+int resolve_precond(gqd_handle* h, int precond, const GammaTab& gt, double dt, bool item_steps) {
+  h->precond_auto = precond == 2 && h->dims == 1;
+  if (precond != 2) {
+    h->stats_precond = precond;
+    return precond;
+  }
+  if (h->dims == 2) {
+    h->stats_precond = 0;
+    return 0;
+  }
+  const double a = 0.5 * std::fabs(dt) * max_abs_tau(gt);
+  for (int c = 0; c < kNumClasses; ++c) {
+    double tmax = 0.0;
+    for (int b : h->class_lists[c]) {
+      const double pmax = M_PI / h->items[b].dq;
+      tmax = std::max(tmax, pmax * pmax / (2.0 * h->mass));
+    }
+    h->class_precond[c] = (item_steps || a * tmax > kPrecondStiffness) ? 1 : 0;
+  }
+  h->stats_precond = 0;
+  return 0;
 }
 
 // Longest-first dispatch: the hardware starts workgroups in launch-list order and a
@@ -349,7 +403,8 @@ gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
     // preconditioned: each iteration also writes and reads z_j = M^-1 v_j, and the
     // cycle's update passes V y through M^-1: 32 (I^2 + 6 I + 10)
     const double pts = h->dims == 2 ? (double)h->n2 * h->n2 : (double)h->items[b].n;
-    const double per_it = h->stats_precond ? 6.0 : 4.0, per_solve = h->stats_precond ? 10.0 : 8.0;
+    const bool pc = h->dims == 1 && h->precond_auto ? h->class_precond[h->items[b].cls] != 0 : h->stats_precond != 0;
+    const double per_it = pc ? 6.0 : 4.0, per_solve = pc ? 10.0 : 8.0;
     st->alg_bytes += 32.0 * pts *
                      ((double)s.iterations_sq + per_it * (double)s.iterations + per_solve * (double)s.solves);
     if ((s.failures || s.nonfinite) && st->failed_item < 0) st->failed_item = b;
@@ -666,7 +721,7 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
     a.psi = (double2*)psi;
     a.work = (double2*)h->work;
     a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-    h->stats_precond = a.sc.precond;
+    a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, false);
     a.method = (m == GQD_TRAP) ? kTrap : kMidp;
     a.dt = dt;
     a.nsteps = nsteps;
@@ -681,7 +736,7 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   a.psi = (double2*)psi;
   a.work = (double2*)h->work;
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-  h->stats_precond = a.sc.precond;
+  a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, dt_item != nullptr);
   a.mode = 0;
   a.method = method_code(m);
   a.dt = dt;
@@ -727,7 +782,7 @@ gqd_status gqd_propagate_noalloc(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   a.psi = (double2*)psi;
   a.work = (double2*)h->scratch;  // nothing in the scratch is read before it is written
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-  h->stats_precond = a.sc.precond;
+  a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, false);
   a.mode = 0;
   a.method = method_code(m);
   a.dt = dt;
@@ -741,6 +796,7 @@ gqd_status gqd_propagate_noalloc(gqd_handle* h, gqd_method m, gqd_scheme sch, in
     a.list = h->d_lists[c];
     a.nlist = (int)h->class_lists[c].size();
     a.tw = h->d_tw + h->tw_off[h->plan[c]];
+    if (h->precond_auto) a.sc.precond = h->class_precond[c];
     GQD_HIP(m == GQD_SPLIT_OPERATOR ? launch_split(h->plan[c], a, strm) : launch_run(h->plan[c], a, strm));
   }
   return st ? collect_stats(h, strm, st) : GQD_OK;
@@ -861,7 +917,7 @@ gqd_status gqd_autotune(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, 
   a.psi = (double2*)psi;
   a.work = (double2*)h->work;
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-  h->stats_precond = a.sc.precond;
+  a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, false);
   a.mode = 0;
   a.method = (m == GQD_TRAP) ? kTrap : kMidp;
   a.dt = dt;
@@ -875,6 +931,7 @@ gqd_status gqd_autotune(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, 
     if (h->class_lists[c].empty()) continue;
     a.list = h->d_lists[c];
     a.nlist = (int)h->class_lists[c].size();
+    if (h->precond_auto) a.sc.precond = h->class_precond[c];
     float best[kMaxPlansPerClass];
     for (int k = 0; k < kMaxPlansPerClass; ++k) best[k] = -1.0f;
     // three rounds over the plans that fit in LDS, keeping each plan's fastest launch
@@ -935,7 +992,7 @@ gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long
     a.gF = gF;
     a.work = (double2*)h->work;
     a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-    h->stats_precond = a.sc.precond;
+    a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, false);
     a.dt = dt;
     a.nsteps = nsteps;
     hipStream_t strm = (hipStream_t)stream;
@@ -951,7 +1008,7 @@ gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long
   a.gF = gF;
   a.work = (double2*)h->work;
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-  h->stats_precond = a.sc.precond;
+  a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, false);
   a.dt = dt;
   a.nsteps = nsteps;
   hipStream_t strm = (hipStream_t)stream;

@@ -9,7 +9,7 @@ from __future__ import annotations
 import ctypes
 import os
 from dataclasses import dataclass
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Union
 
 import numpy as np
 import torch
@@ -134,11 +134,19 @@ class SolverOpts:
     maxit: int = 1000
     literal: bool = False
     verify: bool = False  # end a solve only on a true residual within tol (restart otherwise)
-    precond: bool = False  # right-precondition GMRES by (1 + i a p^2 / 2m)^-1 (1D)
+    # right-precondition GMRES by (1 + i a p^2 / 2m)^-1 (1D); "auto": per size class,
+    # where the kinetic stiffness a T_max of the call exceeds 2
+    precond: Union[bool, str] = False
 
     def c(self) -> _SolverOpts:
+        if isinstance(self.precond, str):
+            if self.precond != "auto":
+                raise ValueError(f"precond must be a bool or 'auto', not {self.precond!r}")
+            pc = 2
+        else:
+            pc = int(bool(self.precond))
         return _SolverOpts(float(self.tol), int(self.restart), int(self.maxit), int(bool(self.literal)),
-                           int(bool(self.verify)), int(bool(self.precond)))
+                           int(bool(self.verify)), pc)
 
 
 @dataclass

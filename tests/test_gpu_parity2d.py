@@ -242,4 +242,9 @@ def test_preconditioner_is_rejected_on_2d_grids(gqd):
     psi = prop.pack([it.psi0])
     with pytest.raises(gqd.GqdError, match="1D grids"):
         prop.propagate(psi, "midp", "suzuki", 2, 10.0, 1, gqd.SolverOpts(tol=1e-14, precond=True))
+    # the automatic choice is the plain solver on 2D grids
+    x, y = prop.pack([it.psi0]), prop.pack([it.psi0])
+    prop.propagate(x, "midp", "suzuki", 2, 10.0, 1, gqd.SolverOpts(tol=1e-14, precond="auto"))
+    prop.propagate(y, "midp", "suzuki", 2, 10.0, 1, gqd.SolverOpts(tol=1e-14))
+    assert torch.equal(x, y)
     prop.close()
