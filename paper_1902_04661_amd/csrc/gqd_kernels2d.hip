@@ -309,6 +309,14 @@ __device__ __forceinline__ void line_fused(const GQD_L cplx* src, GQD_L cplx* ds
 }
 
 // y = IFFT(p FFT x) on the wave's line, both surfaces (x, y: lane's points lane + 64 r).
+// Orders a wave's own LDS passes: every line of a block lives in its wave's own
+// buffers, so the passes need no workgroup barrier.
+__device__ __forceinline__ void line_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int NL>
 __device__ void line_kinetic(const cplx (&x)[2][NL / 64], cplx (&y)[2][NL / 64], const Ctx2& c, double ps) {
   using E = G2<NL>;
@@ -320,35 +328,35 @@ __device__ void line_kinetic(const cplx (&x)[2][NL / 64], cplx (&y)[2][NL / 64],
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int r = 0; r < E::P; ++r) b0[s * NL + lane + 64 * r] = x[s][r];
-  __syncthreads();
+  line_wave_sync();
   const double pn = ps / (double)NL;
   GQD_L cplx* out;
   if constexpr (L::L3 == 1) {
     line_pass<NL, L::L1, -1, false, true>(b0, b1, 1, c);
-    __syncthreads();
+    line_wave_sync();
     line_fused<NL, L::L2, true>(b1, b0, c, pn);
-    __syncthreads();
+    line_wave_sync();
     line_pass<NL, L::L1, 1, true, false>(b0, b1, L::L2, c);
-    __syncthreads();
+    line_wave_sync();
     out = b1;
   } else {
     line_pass<NL, L::L1, -1, false, true>(b0, b1, 1, c);
-    __syncthreads();
+    line_wave_sync();
     line_pass<NL, L::L2, -1, true, false>(b1, b0, L::L1, c);
-    __syncthreads();
+    line_wave_sync();
     line_fused<NL, L::L3, false>(b0, b1, c, pn);
-    __syncthreads();
+    line_wave_sync();
     line_pass<NL, L::L2, 1, true, false>(b1, b0, L::L3, c);
-    __syncthreads();
+    line_wave_sync();
     line_pass<NL, L::L1, 1, false, false>(b0, b1, L::L3 * L::L2, c);
-    __syncthreads();
+    line_wave_sync();
     out = b1;
   }
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int r = 0; r < E::P; ++r) y[s][r] = out[s * NL + lane + 64 * r];
-  __syncthreads();
+  line_wave_sync();
 }
 
 // y += -i F x coupling of A = p - i F: (A x)_1 gains -i F12 x_2, (A x)_2 gains +i F12 x_1
