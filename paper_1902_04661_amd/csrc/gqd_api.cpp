@@ -212,8 +212,9 @@ gqd_status ensure_streams(gqd_handle* h) {
 
 // Launch `fn` once per non-empty size class.  Several classes run concurrently on
 // side streams forked from and joined back into the caller's stream, largest first.
+// class_precond (solves of an automatic call): the preconditioner flag of each class.
 template <class Fn>
-gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
+gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn, const int* class_precond = nullptr) {
   int active = 0;
   for (int c = 0; c < kNumClasses; ++c) active += h->class_lists[c].empty() ? 0 : 1;
   if (active == 1) {
@@ -222,7 +223,7 @@ gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
       a.list = h->d_lists[c];
       a.nlist = (int)h->class_lists[c].size();
       a.tw = h->d_tw + h->tw_off[h->plan[c]];
-      if (h->precond_auto) a.sc.precond = h->class_precond[c];
+      if (class_precond) a.sc.precond = class_precond[c];
       GQD_HIP(fn(h->plan[c], a, stream));
     }
     return GQD_OK;
@@ -238,7 +239,7 @@ gqd_status for_each_class(gqd_handle* h, hipStream_t stream, KArgs a, Fn fn) {
     a.list = h->d_lists[c];
     a.nlist = (int)h->class_lists[c].size();
     a.tw = h->d_tw + h->tw_off[h->plan[c]];
-    if (h->precond_auto) a.sc.precond = h->class_precond[c];
+    if (class_precond) a.sc.precond = class_precond[c];
     GQD_HIP(fn(h->plan[c], a, h->side[c]));
     GQD_HIP(hipEventRecord(h->ev_join[c], h->side[c]));
     GQD_HIP(hipStreamWaitEvent(stream, h->ev_join[c], 0));
@@ -744,7 +745,8 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   a.dt_item = dt_item;
   a.nsteps_item = nsteps_item;
   a.hpsi_valid = 0;
-  s = for_each_class(h, strm, a, m == GQD_SPLIT_OPERATOR ? launch_split : launch_run);
+  s = for_each_class(h, strm, a, m == GQD_SPLIT_OPERATOR ? launch_split : launch_run,
+                     h->precond_auto ? h->class_precond : nullptr);
   if (s != GQD_OK) return s;
   return st ? collect_stats(h, strm, st) : GQD_OK;
 }
@@ -1014,7 +1016,7 @@ gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long
   hipStream_t strm = (hipStream_t)stream;
   a.mode = 1;
   a.method = kMidp;
-  s = for_each_class(h, strm, a, launch_run);
+  s = for_each_class(h, strm, a, launch_run, h->precond_auto ? h->class_precond : nullptr);
   if (s != GQD_OK) return s;
   return st ? collect_stats(h, strm, st) : GQD_OK;
 }

@@ -179,6 +179,16 @@ def test_automatic_preconditioner_takes_each_class_choice(gqd):
           f"{stats['auto'].iterations}, plain {stats[False].iterations}, preconditioned {stats[True].iterations}",
           flush=True)
     assert stats["auto"].alg_bytes == parts
+    # per-item steps stay on the device, so an automatic call preconditions every class
+    small = items[:4]
+    got = {}
+    for pc in (True, "auto"):
+        with gqd.from_items(small) as prop:
+            psi = prop.pack([it.psi0 for it in small])
+            prop.propagate_items(psi, "midp", "suzuki", 6, [2.5] * len(small), [1] * len(small),
+                                 gqd.SolverOpts(tol=1e-17, restart=32, precond=pc))
+            got[pc] = psi.clone()
+    assert torch.equal(got["auto"], got[True])
     with pytest.raises(ValueError):
         gqd.SolverOpts(precond="always").c()
 
