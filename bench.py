@@ -82,12 +82,24 @@ TRAFFIC = {
     "summary": "profiles/k_run_2048_sz8_draws1024_precond.md",
 }
 DEVICE_SOURCES = ["gqd_kernels.hip", "gqd_device.hpp", "gqd_internal.h", "gqd_compositions.h"]
+DEVICE_SOURCES_2D = ["gqd_kernels2d.hip", "gqd_device.hpp", "gqd_internal.h", "gqd_compositions.h"]
+
+# Memory traffic of the 2D kernel (256 x 256, Suzuki-8, dt = 10 a.u., tol 1e-14): the same
+# two counter passes over one 5-step launch, with the same scale factors; reported as a
+# ratio to the algorithmic bytes, valid only for the 2D device sources it was taken on.
+TRAFFIC_2D = {
+    "sources_sha256": "a1252caa7e87f1e641bbe9142bc8d56d92ce5f9a03339d69045c1347b2447392",
+    "fetch_kib": 21493617.625, "fetch_scale": 2.0,
+    "write_kib": 22081934.0625, "write_scale": 1.0,
+    "alg_bytes_same_launch": 39048970240.0,
+    "summary": "profiles/k_run2d_256_sz8.md",
+}
 
 
-def device_sources_sha() -> str:
+def device_sources_sha(names=DEVICE_SOURCES) -> str:
     import hashlib
     outer = hashlib.sha256()
-    for name in DEVICE_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_1902_04661_amd", "csrc", name), "rb") as f:
             outer.update((hashlib.sha256(f.read()).hexdigest() + "  paper_1902_04661_amd/csrc/"
                           + name + "\n").encode())
@@ -100,6 +112,15 @@ def measured_traffic(precond: bool):
         return None, None
     t = 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
     return t, t / TRAFFIC["alg_bytes_same_launch"]
+
+
+def measured_traffic_2d():
+    """Measured over algorithmic bytes of the 2D kernel, or None."""
+    if device_sources_sha(DEVICE_SOURCES_2D) != TRAFFIC_2D["sources_sha256"]:
+        return None
+    t = 1024.0 * (TRAFFIC_2D["fetch_kib"] * TRAFFIC_2D["fetch_scale"]
+                  + TRAFFIC_2D["write_kib"] * TRAFFIC_2D["write_scale"])
+    return t / TRAFFIC_2D["alg_bytes_same_launch"]
 
 
 def alg_bytes(n: int, st) -> float:
@@ -249,12 +270,16 @@ def twod_leg(gqd, inputs, dev, steps: int) -> dict:
         el = time.perf_counter() - t0
         kern = e0.elapsed_time(e1) * 1e-3
     gbs = st.alg_bytes / kern / 1e9
+    ratio = measured_traffic_2d()
     return {"value": 256 * 256 * steps / el, "unit": "grid-point·steps/s", "ms_per_step": 1e3 * el / steps,
             "mean_gmres_iterations": st.iterations / max(st.solves, 1),
             "us_per_h_apply": 1e6 * el / max(st.h_applies, 1),
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS, "kernel": "k_run2d<256>", "launch_ms": kern * 1e3,
-                         "alg_bytes": st.alg_bytes},
+                         "alg_bytes": st.alg_bytes,
+                         "traffic": None if ratio is None else ratio * st.alg_bytes,
+                         "traffic_over_alg_bytes": ratio,
+                         "traffic_source": TRAFFIC_2D["summary"]},
             "workload": f"2D 256x256, Suzuki order 8 midpoint, dt={DT_2D}, {steps} steps, GMRES tol {TOL_2D:g}"}
 
 

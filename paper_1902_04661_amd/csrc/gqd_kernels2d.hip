@@ -22,6 +22,8 @@
 #include "gqd_internal.h"
 #include "gqd_compositions.h"
 
+#include <cstdlib>
+
 namespace gqd {
 
 template <int NL>
@@ -1266,10 +1268,27 @@ hipError_t max_resident2d(int cls, int m, int* blocks) {
   return hipSuccess;
 }
 
+// The launch is cooperative, so the runtime guarantees that every workgroup is resident.
+// GQD_2D_PLAIN_LAUNCH=1 in the environment makes it an ordinary launch of the same grid
+// instead, for profilers that fail on cooperative launches: the grid never exceeds the
+// resident capacity (run2d sizes it so), so on an otherwise idle GPU every workgroup
+// starts at once; if one could not, the waits of the others end at their poll limit and
+// the call fails with the barrier time-out.
+static bool plain_launch_2d() {
+  const char* v = std::getenv("GQD_2D_PLAIN_LAUNCH");
+  return v && v[0] == '1' && v[1] == 0;
+}
+
 hipError_t launch_run2d(int cls, const K2Args& a, hipStream_t stream) {
   K2Args args = a;
   void* params[] = {&args};
+  const bool plain = plain_launch_2d();
   GQD_DISPATCH2(cls, {
+    if (plain) {
+      hipLaunchKernelGGL(k_run2d<NL>, dim3(a.batch * a.G * a.roles), dim3(kThreads2), lds_bytes2(NL, a.sc.m),
+                         stream, args);
+      return hipGetLastError();
+    }
     return hipLaunchCooperativeKernel((const void*)k_run2d<NL>, dim3(a.batch * a.G * a.roles), dim3(kThreads2), params,
                                       (unsigned)lds_bytes2(NL, a.sc.m), stream);
   });

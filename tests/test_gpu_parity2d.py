@@ -248,3 +248,19 @@ def test_preconditioner_is_rejected_on_2d_grids(gqd):
     prop.propagate(y, "midp", "suzuki", 2, 10.0, 1, gqd.SolverOpts(tol=1e-14))
     assert torch.equal(x, y)
     prop.close()
+
+
+def test_plain_launch_matches_cooperative_2d(gqd, monkeypatch):
+    # GQD_2D_PLAIN_LAUNCH=1 launches the same grid as an ordinary kernel (for profilers
+    # that fail on cooperative launches): the results must not change by a bit
+    it = moving_item(128, seed=4, p0=(1.5, -1.0))
+    prop = gqd.from_items([it])
+    x, y = prop.pack([it.psi0]), prop.pack([it.psi0])
+    opts = gqd.SolverOpts(tol=1e-14)
+    sx = prop.propagate(x, "midp", "suzuki", 4, 10.0, 2, opts)
+    monkeypatch.setenv("GQD_2D_PLAIN_LAUNCH", "1")
+    sy = prop.propagate(y, "midp", "suzuki", 4, 10.0, 2, opts)
+    monkeypatch.delenv("GQD_2D_PLAIN_LAUNCH")
+    print(f"cooperative {sx.iterations} iterations, ordinary launch {sy.iterations}", flush=True)
+    assert torch.equal(x, y) and sx.iterations == sy.iterations
+    prop.close()
