@@ -737,7 +737,8 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   a.psi = (double2*)psi;
   a.work = (double2*)h->work;
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-  a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, dt_item != nullptr);
+  // (the implicit Euler step solves 1 + i dt H: its half-substep is the whole step)
+  a.sc.precond = resolve_precond(h, o->precond, a.gt, elementary(m) ? 2.0 * dt : dt, dt_item != nullptr);
   a.mode = 0;
   a.method = method_code(m);
   a.dt = dt;
@@ -784,7 +785,7 @@ gqd_status gqd_propagate_noalloc(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   a.psi = (double2*)psi;
   a.work = (double2*)h->scratch;  // nothing in the scratch is read before it is written
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-  a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, false);
+  a.sc.precond = resolve_precond(h, o->precond, a.gt, elementary(m) ? 2.0 * dt : dt, false);
   a.mode = 0;
   a.method = method_code(m);
   a.dt = dt;
