@@ -6,8 +6,10 @@
 //     multidimensional form, Sec. II.E) splits into line operations: A_2 acts along
 //     rows (fixed q1), A_1 along columns (fixed q2), each line independent.  A line
 //     block is kLineWaves adjacent lines, one wave per line: the block is staged
-//     through LDS with coalesced loads, each wave runs its line's radix-4 Stockham
-//     transforms in its own LDS buffers, and the block is written back.  Row blocks
+//     through LDS with coalesced loads, each wave runs its line's Stockham transforms
+//     (radix 8 where the line allows, the k-space multiply fused between the last
+//     forward and the first inverse pass) in its own LDS buffers, and the block is
+//     written back.  Row blocks
 //     also add V psi; rows and columns write two separate partial results.
 //   * every other vector operation (Gram-Schmidt, updates, norms) runs on contiguous
 //     chunks of VEC / G elements per workgroup; a reduction writes one partial per
