@@ -424,7 +424,13 @@ __device__ void line_op(const LineReq& q, const Ctx2& c, const K2Args& a, const 
   const double* F = a.F + im.off;
   for (int b = g; b < 2 * E::NBA; b += a.G) {
     const bool row = b < E::NBA;
-    const int l0 = (row ? b : b - E::NBA) * kLineWaves;
+    // Column slot j = 16 q + 8 h + r takes column block 2 (8 q + r) + h: the two blocks
+    // whose four columns share 128-byte lines (blocks 2k and 2k + 1) go to workgroups
+    // eight apart, which the dispatcher places on the same XCD, so one L2 serves both
+    // halves of every line.
+    const int cj = b - E::NBA;
+    const int cb = 2 * (8 * (cj >> 4) + (cj & 7)) + ((cj >> 3) & 1);
+    const int l0 = (row ? b : cb) * kLineWaves;
     // EB elements per thread at a time, each source read for all of them before any is
     // used, so that a wave keeps EB loads in flight (per element the operations and
     // their order are those of the formula above)
