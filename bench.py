@@ -88,9 +88,9 @@ DEVICE_SOURCES_2D = ["gqd_kernels2d.hip", "gqd_device.hpp", "gqd_internal.h", "g
 # two counter passes over one 5-step launch, with the same scale factors; reported as a
 # ratio to the algorithmic bytes, valid only for the 2D device sources it was taken on.
 TRAFFIC_2D = {
-    "sources_sha256": "7634f1b3a2b61b706077ae6aaa1d0fa62787486eb37357fc9d2ca9fa511627db",
-    "fetch_kib": 9671743.875, "fetch_scale": 2.0,
-    "write_kib": 22081934.0625, "write_scale": 1.0,
+    "sources_sha256": "bb8c9a7cdae4aeca1ee006b3bcbe54ac7a6af9ea2b3f8737279736fc0444cb5a",
+    "fetch_kib": 14936563.125, "fetch_scale": 2.0,
+    "write_kib": 20801486.0625, "write_scale": 1.0,
     "alg_bytes_same_launch": 39048970240.0,
     "summary": "profiles/k_run2d_256_sz8.md",
 }

@@ -393,7 +393,7 @@ __device__ __forceinline__ void block_map(bool row, int e, int& s, int& w, int& 
 }
 
 // Line operation request of the propagation machine.
-// The operand is x = scale * (src + src2 - i hal (h1 + h2) - sum_{i<K} coef_i basis_i)
+// The operand is x = scale * (srcw src + src2w src2 - i hal (h1 + h2) - sum_{i<K} coef_i basis_i)
 // (src2, h1, h2 may be null, coef in LDS); row and column blocks form it with the same
 // operations, so both see the same values, and row blocks store it to copy_dst.  The
 // h term forms (1 - i al H) b from b and the two halves of H b (or a stored H b), so a
@@ -414,6 +414,8 @@ struct LineReq {
   const cplx* h1 = nullptr;
   const cplx* h2 = nullptr;
   double hal = 0.0;
+  double srcw = 1.0;   // weights of src and src2 (applied only when not 1)
+  double src2w = 1.0;
 };
 
 template <int NL>
@@ -465,7 +467,15 @@ __device__ void line_op(const LineReq& q, const Ctx2& c, const K2Args& a, const 
 #pragma unroll
         for (int u = 0; u < EB; ++u) t3[u] = q.h2[gi[u]];
       }
+      if (q.srcw != 1.0) {
+#pragma unroll
+        for (int u = 0; u < EB; ++u) v[u] = cscale(v[u], q.srcw);
+      }
       if (q.src2) {
+        if (q.src2w != 1.0) {
+#pragma unroll
+          for (int u = 0; u < EB; ++u) t[u] = cscale(t[u], q.src2w);
+        }
 #pragma unroll
         for (int u = 0; u < EB; ++u) v[u] = cadd(v[u], t[u]);
       }
@@ -677,6 +687,12 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   double alpha = 0.0;
 
   bool pending = false, swap_after = false;
+  // Midpoint fold: a converged solve that is not the call's last leaves x = x0 + V y and
+  // psi' = 2 x - psi to the load of the next substep's first H request, which forms
+  // psi' = 2 x0 + 2 V y - psi and stores it to the other buffer of the pair (psi, HP);
+  // fold_k > 0: pending, with y in LDS and fold_k basis vectors
+  int fold_k = 0;
+  cplx* psi_cur = psi;
   LineReq rq{};
   const cplx* bg = nullptr;
   cplx* xg = nullptr;
@@ -848,7 +864,20 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         } else if (adj) {
           solve_begin(psi, X, -alpha, k2AdjAfterPhi);
         } else if (midp) {
-          solve_begin(psi, X, alpha, k2MidpAfter);
+          if (fold_k > 0) {
+            // b = 2 x0 + 2 V y - psi, formed by the load of H b and stored to the other buffer
+            for (int i = threadIdx.x; i < fold_k; i += T) c.coef[i] = cscale(c.y[i], -2.0);
+            __syncthreads();
+            cplx* nb = psi_cur == psi ? HP : psi;
+            LineReq pre{X, psi_cur, basis, fold_k, mk(1.0, 0.0), false, nb, true, ORs, OCs};
+            pre.srcw = 2.0;
+            pre.src2w = -1.0;
+            psi_cur = nb;
+            fold_k = 0;
+            solve_begin(psi_cur, X, alpha, k2MidpAfter, &pre);
+          } else {
+            solve_begin(psi_cur, X, alpha, k2MidpAfter);
+          }
         } else if (literal || !have_hpsi) {
           request(psi, true);
           pc = k2TrapHpsi;
@@ -885,7 +914,13 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
           pc = k2MidpExplicit;
           break;
         }
-        for (long long e = e0 + threadIdx.x; e < e1; e += T) psi[e] = csub(cscale(X[e], 2.0), psi[e]);
+        if (fold_k > 0) {  // the next substep's first load forms psi'
+          advance();
+          break;
+        }
+        // into the caller's buffer, whichever of the pair holds psi now
+        for (long long e = e0 + threadIdx.x; e < e1; e += T) psi[e] = csub(cscale(X[e], 2.0), psi_cur[e]);
+        psi_cur = psi;
         touched = true;
         advance();
         break;
@@ -1060,6 +1095,14 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         }
         const int k = j + 1;
         gm_back_solve(k, c);
+        if (cv && !a.sc.verify && after == k2MidpAfter && !literal && !adj &&
+            !(cc + 1 == a.gt.count && n + 1 >= nsteps)) {
+          // a midpoint solve with a substep after it in this call: x = x0 + V y and the
+          // update psi' = 2x - psi go into the next H request's load (fold_k)
+          fold_k = k;
+          solve_end(true);
+          break;
+        }
         for (long long eb = e0 + threadIdx.x; eb < e1; eb += kChunkB * T) {
           cplx x[kChunkB], t[kChunkB];
 #pragma unroll
