@@ -39,8 +39,9 @@
  * workspace, gqd_propagate_items is unsupported.  gqd_adjoint gives each item two
  * groups, one for the phi solves and one for the mu solves of every substep, so a 2D
  * workspace holds two regions per item.  The group crosses grid barriers with
- * a bounded wait: if one ever times out the item stops and a call given a gqd_stats
- * pointer returns GQD_ERR_HIP.  With GQD_2D_PLAIN_LAUNCH=1 in the environment the 2D
+ * a bounded wait: if one ever times out the item stops, its state is left unspecified
+ * (within a call the midpoint rule may hold it in the workspace), and a call given a
+ * gqd_stats pointer returns GQD_ERR_HIP.  With GQD_2D_PLAIN_LAUNCH=1 in the environment the 2D
  * kernel is launched as an ordinary kernel of the same grid instead (for profilers
  * that fail on cooperative launches); the grid never exceeds what can be resident, so
  * on an otherwise idle GPU nothing changes, and a workgroup that could not start would
