@@ -170,6 +170,15 @@ typedef struct {
                             on a true residual: every solve with verify = 1; without it
                             only those that ended at their initial residual or after a
                             restart (0 if none did) */
+  double impl_bytes;    /* alg_bytes plus the vector passes this implementation makes
+                           beyond them, 32 bytes per grid point each: both sweeps (dot
+                           products and update) of every second Gram-Schmidt pass, 2(j + 1)
+                           vectors at Arnoldi step j; the dot products of the plain 1D
+                           solver's three-term pre-projection (v_j, v_(j-1)); the
+                           preconditioned solver's second read of v_j, which its
+                           shifted Arnoldi step subtracts (1 per iteration); with
+                           literal = 1, the explicit half-step's H application (2 per
+                           solve).  Reads served from LDS count as well */
 } gqd_stats;
 
 typedef struct gqd_handle gqd_handle;

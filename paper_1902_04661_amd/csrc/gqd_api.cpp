@@ -62,6 +62,7 @@ struct gqd_handle {
   int resident_cap = 0;  // workgroups the partial and sync areas are sized for
   int stats_roles = 1;   // groups per item of the last 2D launch (2: merge their statistics)
   int stats_precond = 0; // the last launch's solves were preconditioned (byte count)
+  int stats_literal = 0; // the last launch ran the literal explicit half-steps (byte count)
   // precond = 2 (automatic): the choice of each size class for the current call
   bool precond_auto = false;
   int class_precond[kNumClasses] = {};
@@ -309,7 +310,8 @@ double max_abs_tau(const GammaTab& gt) {
   return t;
 }
 
-// Solver option precond (0 off, 1 on, 2 automatic) resolved for one call; returns the
+// Solver option precond (0 off, 1 on, 2 automatic) resolved for one call (the byte
+// counts of the call's statistics also note its literal flag here); returns the
 // flag the launch arguments carry (for automatic calls, each size class then takes its
 // own from class_precond).  The kinetic part sets the stiffness of 1 + i a H: with
 // T_max = (pi / dq)^2 / 2m the largest kinetic energy of a class's grids and a the
@@ -320,7 +322,9 @@ double max_abs_tau(const GammaTab& gt) {
 // one twice as fast at 5.7; the 8th-order batch at 20 a.u., a T_max = 5.0, 1.8x).
 // With per-item steps (not read back from the device) an automatic call
 // preconditions every class.
-int resolve_precond(gqd_handle* h, int precond, const GammaTab& gt, double dt, bool item_steps) {
+int resolve_precond(gqd_handle* h, const gqd_solver_opts* o, const GammaTab& gt, double dt, bool item_steps) {
+  const int precond = o->precond;
+  h->stats_literal = o->literal ? 1 : 0;
   h->precond_auto = precond == 2 && h->dims == 1;
   if (precond != 2) {
     h->stats_precond = precond;
@@ -377,6 +381,7 @@ gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
       s.h_applies += s1[b].h_applies;
       s.iterations += s1[b].iterations;
       s.iterations_sq += s1[b].iterations_sq;
+      s.extra_vecs += s1[b].extra_vecs;
       s.solves += s1[b].solves;
       if (s1[b].max_iters > s.max_iters) s.max_iters = s1[b].max_iters;
       s.failures += s1[b].failures;
@@ -406,8 +411,12 @@ gqd_status collect_stats(gqd_handle* h, hipStream_t stream, gqd_stats* st) {
     const double pts = h->dims == 2 ? (double)h->n2 * h->n2 : (double)h->items[b].n;
     const bool pc = h->dims == 1 && h->precond_auto ? h->class_precond[h->items[b].cls] != 0 : h->stats_precond != 0;
     const double per_it = pc ? 6.0 : 4.0, per_solve = pc ? 10.0 : 8.0;
-    st->alg_bytes += 32.0 * pts *
-                     ((double)s.iterations_sq + per_it * (double)s.iterations + per_solve * (double)s.solves);
+    const double alg = 32.0 * pts *
+                       ((double)s.iterations_sq + per_it * (double)s.iterations + per_solve * (double)s.solves);
+    st->alg_bytes += alg;
+    // implementation bytes: the extra Gram-Schmidt sweeps, and in literal mode the
+    // explicit half-step's own H application (read and write, per solve)
+    st->impl_bytes += alg + 32.0 * pts * ((double)s.extra_vecs + (h->stats_literal ? 2.0 * (double)s.solves : 0.0));
     if ((s.failures || s.nonfinite) && st->failed_item < 0) st->failed_item = b;
   }
   for (int b = 0; b < h->batch; ++b)
@@ -722,7 +731,7 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
     a.psi = (double2*)psi;
     a.work = (double2*)h->work;
     a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-    a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, false);
+    a.sc.precond = resolve_precond(h, o, a.gt, dt, false);
     a.method = (m == GQD_TRAP) ? kTrap : kMidp;
     a.dt = dt;
     a.nsteps = nsteps;
@@ -738,7 +747,7 @@ static gqd_status propagate_impl(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   a.work = (double2*)h->work;
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
   // (the implicit Euler step solves 1 + i dt H: its half-substep is the whole step)
-  a.sc.precond = resolve_precond(h, o->precond, a.gt, elementary(m) ? 2.0 * dt : dt, dt_item != nullptr);
+  a.sc.precond = resolve_precond(h, o, a.gt, elementary(m) ? 2.0 * dt : dt, dt_item != nullptr);
   a.mode = 0;
   a.method = method_code(m);
   a.dt = dt;
@@ -785,7 +794,7 @@ gqd_status gqd_propagate_noalloc(gqd_handle* h, gqd_method m, gqd_scheme sch, in
   a.psi = (double2*)psi;
   a.work = (double2*)h->scratch;  // nothing in the scratch is read before it is written
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-  a.sc.precond = resolve_precond(h, o->precond, a.gt, elementary(m) ? 2.0 * dt : dt, false);
+  a.sc.precond = resolve_precond(h, o, a.gt, elementary(m) ? 2.0 * dt : dt, false);
   a.mode = 0;
   a.method = method_code(m);
   a.dt = dt;
@@ -920,7 +929,7 @@ gqd_status gqd_autotune(gqd_handle* h, gqd_method m, gqd_scheme sch, int order, 
   a.psi = (double2*)psi;
   a.work = (double2*)h->work;
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-  a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, false);
+  a.sc.precond = resolve_precond(h, o, a.gt, dt, false);
   a.mode = 0;
   a.method = (m == GQD_TRAP) ? kTrap : kMidp;
   a.dt = dt;
@@ -995,7 +1004,7 @@ gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long
     a.gF = gF;
     a.work = (double2*)h->work;
     a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-    a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, false);
+    a.sc.precond = resolve_precond(h, o, a.gt, dt, false);
     a.dt = dt;
     a.nsteps = nsteps;
     hipStream_t strm = (hipStream_t)stream;
@@ -1011,7 +1020,7 @@ gqd_status gqd_adjoint(gqd_handle* h, gqd_scheme sch, int order, double dt, long
   a.gF = gF;
   a.work = (double2*)h->work;
   a.sc = SolveCfg{o->tol, o->restart, o->maxit, o->literal ? 1 : 0, o->verify ? 1 : 0, o->precond ? 1 : 0};
-  a.sc.precond = resolve_precond(h, o->precond, a.gt, dt, false);
+  a.sc.precond = resolve_precond(h, o, a.gt, dt, false);
   a.dt = dt;
   a.nsteps = nsteps;
   hipStream_t strm = (hipStream_t)stream;

@@ -34,6 +34,10 @@ struct ItemStats {
   long long h_applies;
   long long iterations;
   long long iterations_sq;  // sum over solves of (iterations of the solve)^2
+  // vector passes beyond the algorithmic count: the three-term pre-projection's dot
+  // products, the preconditioned Arnoldi step's read of v_j for its shift and both
+  // sweeps of every second Gram-Schmidt pass
+  long long extra_vecs;
   int solves;
   int max_iters;
   int failures;         // solves that hit maxit

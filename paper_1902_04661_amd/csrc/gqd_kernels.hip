@@ -1070,7 +1070,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
   const long long nsteps = a.nsteps_item ? a.nsteps_item[item] : a.nsteps;
   const bool literal = a.sc.literal != 0;
 
-  long long napply = 0, iters_total = 0, iters_sq = 0;
+  long long napply = 0, iters_total = 0, iters_sq = 0, extra_vecs = 0;
   int solves = 0, max_iters = 0, failures = 0;
   bool bad = false;
   bool have_hpsi = a.hpsi_valid != 0;
@@ -1092,6 +1092,9 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
   // Arnoldi runs on H - s, s the Rayleigh quotient of the first basis vector of the
   // previous solve of the same kind (sig0: psi or phi, sig1: the adjoint's mu)
   double sig0 = 0.0, sig1 = 0.0;
+  // preconditioned solves run Arnoldi on X M^-1 - (1 + i al e), e = (h_00 - 1) / (i al)
+  // taken from the first column of the previous solve of the same kind
+  cplx pe0 = mk(0.0, 0.0), pe1 = mk(0.0, 0.0);
   bool kind_mu = false;
   // solve state
   const cplx* bg = nullptr;
@@ -1409,19 +1412,29 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
       }
       case kPrecArnoldi: {
         if constexpr (PC) {
-          // Arnoldi step j on X M^-1 (right preconditioning): w = z_j + i al H z_j, one
-          // classical Gram-Schmidt pass over v_0..v_j with |w|^2 from the same reduction,
-          // a second pass when the first keeps less than kReorthRatio of |w|^2.  X M^-1
-          // has no Hermitian structure to exploit, and the column is X M^-1's own.
+          // Arnoldi step j on X M^-1 (right preconditioning), shifted by s = 1 + i al e:
+          // w = z_j + i al H z_j - s v_j, one classical Gram-Schmidt pass over v_0..v_j
+          // with |w|^2 from the same reduction, a second pass when the first keeps less
+          // than kReorthRatio of |w|^2.  X M^-1 = 1 + i al (H - T) M^-1 has no Hermitian
+          // structure to exploit.  Unshifted, w lies mostly along v_j (the identity and
+          // the potential's mean), the pass cancels most of |w|^2 and the second pass
+          // runs on nearly every step; with e the Rayleigh energy of the previous solve
+          // of the same kind it cancels little.  The shift changes the Krylov space of
+          // no step; the column of X M^-1 gains s on its diagonal below.
           ++iters;
+          const cplx pe = kind_mu ? pe1 : pe0;
+          const cplx sft = mk(1.0 - al * pe.y, al * pe.x);
           {
-            OV z;
+            OV z, v;
             E::load(z, S3);
+            E::load(v, basis + (size_t)j * E::VEC);
 #pragma unroll
             for (int s = 0; s < 2; ++s)
 #pragma unroll
-              for (int r = 0; r < R0; ++r) y.v[s][r] = cadd(z.v[s][r], cmul_is(y.v[s][r], al));
+              for (int r = 0; r < R0; ++r)
+                y.v[s][r] = csub(cadd(z.v[s][r], cmul_is(y.v[s][r], al)), cmul(sft, v.v[s][r]));
           }
+          extra_vecs += 1;  // v_j read again for the shift
           E::template block_dots<E::kStashOff>(basis, y, j + 1, c, c.hcol, true);
           const double w2 = uniform_d(c.hcol[j + 1].x);
           double hn2 = w2;
@@ -1429,6 +1442,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           hn2 = uniform_d(hn2);
           E::template block_axpy<false>(basis, c.hcol, j + 1, y, c);
           if (hn2 < kReorthRatio * w2) {
+            extra_vecs += 2 * (j + 1);
             E::template block_dots<E::kStashOff>(basis, y, j + 1, c, c.y, true);
             double r2 = uniform_d(c.y[j + 1].x);
             for (int i = 0; i <= j; ++i) r2 -= cabs2(c.y[i]);
@@ -1439,8 +1453,15 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
             for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);
           }
           __syncthreads();
+          // the same thread rotates the column next
+          if (threadIdx.x == 0) c.hcol[j] = cadd(c.hcol[j], sft);
           const double hn = sqrt(hn2);
           E::givens_update(j, hn, c);
+          if (j == 0 && al != 0.0) {  // h_00 is left in place by the first rotation
+            const double h0x = uniform_d(c.hcol[0].x), h0y = uniform_d(c.hcol[0].y);
+            const cplx e = mk(h0y / al, (1.0 - h0x) / al);  // (h_00 - 1) / (i al)
+            if (kind_mu) pe1 = e; else pe0 = e;
+          }
           const double gabs = uniform_d(c.scal[0]);
           if (!isfinite(hn) || !isfinite(gabs)) {
             bad = true;
@@ -1529,6 +1550,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         const cplx* b0 = basis + (size_t)k0 * E::VEC;
         E::template block_dots<E::kStashFill>(b0, y, K0, c, c.y, false);
         E::template block_axpy<true>(b0, c.y, K0, y, c);
+        extra_vecs += K0;
         // |w2|^2 = |w1|^2 - sum |c_i|^2 when the pass keeps at least half of |w1|^2 (a
         // few ulp there); a further pass returns its own |w'|^2 from the same reduction
         E::template block_dots<E::kStashFill>(basis, y, j + 1, c, c.hcol, true);
@@ -1548,6 +1570,7 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         if (threadIdx.x < K0) c.hcol[k0 + threadIdx.x] = cadd(c.hcol[k0 + threadIdx.x], c.y[threadIdx.x]);
         __syncthreads();
         if (hn2 < kReorthRatio * w2) {
+          extra_vecs += 2 * (j + 1);
           E::template block_dots<E::kStashUse>(basis, y, j + 1, c, c.y, true);
           double r2 = uniform_d(c.y[j + 1].x);
           for (int i = 0; i <= j; ++i) r2 -= cabs2(c.y[i]);
@@ -1762,6 +1785,7 @@ done:
     st->h_applies = napply;
     st->iterations = iters_total;
     st->iterations_sq = iters_sq;
+    st->extra_vecs = extra_vecs;
     st->solves = solves;
     st->max_iters = max_iters;
     st->failures = failures;

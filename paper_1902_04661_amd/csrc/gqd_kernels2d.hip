@@ -676,7 +676,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
   const double dt = a.dt;
   const long long nsteps = a.nsteps;
 
-  long long napply = 0, iters_total = 0, iters_sq = 0;
+  long long napply = 0, iters_total = 0, iters_sq = 0, extra_vecs = 0;
   int solves = 0, max_iters = 0, failures = 0;
   bool bad = false, aborted = false;
   bool have_hpsi = false;
@@ -1027,6 +1027,7 @@ __global__ void __launch_bounds__(kThreads2) k_run2d(K2Args a) {
         const cplx* base = OR;
         const cplx* base2 = OC;
         if (hn2 < kReorthRatio * w2) {
+          extra_vecs += 2 * (j + 1);
           // second pass: W = w - sum h_i v_i, then c_i = <v_i, W> and |W|^2 in one
           // reduction; the update by c is left to the next operand load
           for (long long eb = e0 + threadIdx.x; eb < e1; eb += kChunkB * T) {
@@ -1274,6 +1275,7 @@ done:
     st->h_applies = napply;
     st->iterations = iters_total;
     st->iterations_sq = iters_sq;
+    st->extra_vecs = extra_vecs;
     st->solves = solves;
     st->max_iters = max_iters;
     st->failures = failures;

@@ -62,7 +62,7 @@ class _Stats(ctypes.Structure):
                 ("solves", ctypes.c_longlong), ("max_iters", ctypes.c_int),
                 ("failures", ctypes.c_int), ("failed_item", ctypes.c_int),
                 ("nonfinite", ctypes.c_int), ("alg_bytes", ctypes.c_double),
-                ("max_true_resid", ctypes.c_double)]
+                ("max_true_resid", ctypes.c_double), ("impl_bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -161,13 +161,14 @@ class Stats:
     nonfinite: int
     alg_bytes: float
     max_true_resid: float
+    impl_bytes: float
 
 
 def _stats(st) -> Optional[Stats]:
     if st is None:
         return None
     return Stats(st.h_applies, st.iterations, st.iterations_sq, st.solves, st.max_iters,
-                 st.failures, st.failed_item, st.nonfinite, st.alg_bytes, st.max_true_resid)
+                 st.failures, st.failed_item, st.nonfinite, st.alg_bytes, st.max_true_resid, st.impl_bytes)
 
 
 def _stream_ptr(stream=None):

@@ -193,6 +193,25 @@ def test_automatic_preconditioner_takes_each_class_choice(gqd):
         gqd.SolverOpts(precond="always").c()
 
 
+def test_implementation_bytes_count_the_extra_sweeps(gqd):
+    # impl_bytes - alg_bytes is 32 bytes per grid point per extra vector pass: the plain
+    # solver's three-term pre-projection (one vector at j = 0, two after: 2 I - 1 per
+    # solve), the preconditioned solver's second read of v_j for its shift (I per solve),
+    # literal mode's explicit half-step (2 per solve), and both sweeps of every second
+    # Gram-Schmidt pass (an even count)
+    it = I.nai_like_item(1024, p0=3.0)
+    for literal, precond in ((False, False), (True, False), (False, True)):
+        with gqd.from_items([it]) as prop:
+            psi = prop.pack([it.psi0])
+            st = prop.propagate(psi, "midp", "suzuki", 4, 10.0, 2,
+                                gqd.SolverOpts(tol=1e-14, literal=literal, precond=precond))
+        extra = (st.impl_bytes - st.alg_bytes) / (32.0 * it.n)
+        base = (st.iterations if precond else 2 * st.iterations - st.solves) + (2 * st.solves if literal else 0)
+        print(f"literal={literal} precond={precond}: {extra:.0f} extra vector passes, {base} without "
+              f"second passes, {st.iterations} iterations in {st.solves} solves", flush=True)
+        assert extra == round(extra) and extra >= base and (round(extra) - base) % 2 == 0
+
+
 def test_preconditioned_restarts_verify_and_adjoint_match_oracle(gqd):
     it = I.nai_like_item(1024, q0=4.6, p0=-4.0, amp=0.7)
     m = O.model_from_item(it)

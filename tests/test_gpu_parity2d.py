@@ -264,3 +264,16 @@ def test_plain_launch_matches_cooperative_2d(gqd, monkeypatch):
     print(f"cooperative {sx.iterations} iterations, ordinary launch {sy.iterations}", flush=True)
     assert torch.equal(x, y) and sx.iterations == sy.iterations
     prop.close()
+
+
+def test_implementation_bytes_count_second_passes_2d(gqd):
+    # the 2D solver makes no three-term pre-projection: the extra vector passes are both
+    # sweeps of its second Gram-Schmidt passes, an even count
+    it = moving_item(64, seed=5)
+    prop = gqd.from_items([it])
+    psi = prop.pack([it.psi0])
+    st = prop.propagate(psi, "midp", "suzuki", 4, 10.0, 2, gqd.SolverOpts(tol=1e-14))
+    extra = (st.impl_bytes - st.alg_bytes) / (32.0 * 64 * 64)
+    print(f"2D: {extra:.0f} extra vector passes, {st.iterations} iterations", flush=True)
+    assert extra == round(extra) and extra >= 0 and round(extra) % 2 == 0
+    prop.close()
