@@ -971,6 +971,31 @@ struct Eng {
   // --------------------------------------------------------------------- GMRES
   static __device__ void givens_update(int j, double hn, const Ctx& c) { gm_givens(j, hn, c); }
   static __device__ void back_solve(int k, const Ctx& c) { gm_back_solve(k, c); }
+
+  // |g_(j+1)| that givens_update would leave for the column hcol + dj e_j and the
+  // subdiagonal hn, in the same arithmetic, writing nothing (thread 0's value counts)
+  static __device__ double givens_probe(int j, double hn, cplx dj, const Ctx& c) {
+    const GQD_L cplx* h = c.hcol;
+    cplx a = j == 0 ? cadd(h[0], dj) : h[0];
+    for (int i = 0; i < j; ++i) {
+      const double ci = c.cs[i];
+      const cplx si = c.sn[i];
+      const cplx hi1 = i + 1 == j ? cadd(h[j], dj) : h[i + 1];
+      a = cadd(cmul(cneg(mk(si.x, -si.y)), a), cscale(hi1, ci));
+    }
+    cplx sj;
+    if (hn == 0.0) {
+      sj = mk(0.0, 0.0);
+    } else if (a.x == 0.0 && a.y == 0.0) {
+      sj = mk(1.0, 0.0);
+    } else {
+      const double absa = hypot(a.x, a.y);
+      const double rho = sqrt(absa * absa + hn * hn);
+      sj = cscale(mk(a.x / absa, a.y / absa), hn / rho);
+    }
+    const cplx g1 = cmul(cneg(mk(sj.x, -sj.y)), c.g[j]);
+    return hypot(g1.x, g1.y);
+  }
 };
 
 // composition fraction tau_c: product of one gamma per level, innermost level first
@@ -1441,7 +1466,21 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           for (int i = 0; i <= j; ++i) hn2 -= cabs2(c.hcol[i]);
           hn2 = uniform_d(hn2);
           E::template block_axpy<false>(basis, c.hcol, j + 1, y, c);
-          if (hn2 < kReorthRatio * w2) {
+          // The second pass only serves v_(j+1).  Where it is due, the step is most often
+          // the cycle's last (the new direction is small against w as the residual
+          // estimate reaches the tolerance), which the one-pass column decides as well:
+          // the tolerance met, the restart length or maxit reached.  Those steps skip it.
+          bool reorth = hn2 < kReorthRatio * w2;
+          if (reorth && hn2 > 0.0) {
+            if (iters >= a.sc.maxit || j + 1 >= m) {
+              reorth = false;
+            } else {
+              if (threadIdx.x == 0) c.scal[1] = E::givens_probe(j, sqrt(hn2), sft, c);
+              __syncthreads();
+              reorth = !(uniform_d(c.scal[1]) <= tolb);
+            }
+          }
+          if (reorth) {
             extra_vecs += 2 * (j + 1);
             E::template block_dots<E::kStashOff>(basis, y, j + 1, c, c.y, true);
             double r2 = uniform_d(c.y[j + 1].x);
