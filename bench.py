@@ -74,10 +74,10 @@ TOL_ADJ = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "b3e724dec17f0768c2ac24cc715359b955e69365f3093c2bd9851d6655809946",
-    "fetch_kib": 177277531.9375, "fetch_scale": 2.0,
-    "write_kib": 108922141.75, "write_scale": 1.0,
-    "alg_bytes_same_launch": 587775868928.0,
+    "sources_sha256": "2fc74282d7c941ea3122151c1f79e2c3e0f7db92366a7b79a4f7e22d7b1c9556",
+    "fetch_kib": 168158312.75, "fetch_scale": 2.0,
+    "write_kib": 108957182.875, "write_scale": 1.0,
+    "alg_bytes_same_launch": 587776983040.0,
     "precond": True,
     "summary": "profiles/k_run_2048_sz8_draws1024_precond.md",
 }
@@ -158,7 +158,7 @@ def ragged_leg(gqd, inputs, dev, batch: int, steps: int) -> dict:
     import torch
     items = inputs.ragged_batch(batch, seed=0)
     # each size class with the solver its kinetic stiffness calls for (at 2.5 a.u. the
-    # preconditioner pays on the N = 4096 grids only)
+    # preconditioner pays on the N = 2048 and 4096 grids)
     opts = gqd.SolverOpts(tol=TOL, restart=32, precond="auto")
     with gqd.from_items(items, device=dev) as prop:
         psi = prop.pack([it.psi0 for it in items])

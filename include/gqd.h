@@ -143,7 +143,7 @@ typedef struct {
                   stiffness of the system on fine grids: about 4.6 iterations per solve
                   instead of 10 at N = 2048 and 21 at N = 4096.  1D grids only
                   (GQD_ERR_UNSUPPORTED on 2D).  0: plain GMRES, as in Sec. II.C.
-                  2: automatic, per size class: preconditioned where a T_max > 2, with
+                  2: automatic, per size class: preconditioned where a T_max > 1.25, with
                   a the call's largest half-substep |tau_c dt| / 2 and T_max the
                   largest kinetic energy (pi / dq)^2 / 2m of the class's grids, plain
                   elsewhere (where the extra transforms cost more than the saved

@@ -42,7 +42,7 @@ int class_of(int n) {
 
 constexpr size_t kLdsMax = 160 * 1024;
 // a T_max above which an automatic call preconditions a size class (resolve_precond)
-constexpr double kPrecondStiffness = 2.0;
+constexpr double kPrecondStiffness = 1.25;
 
 }  // namespace
 
@@ -317,9 +317,10 @@ double max_abs_tau(const GammaTab& gt) {
 // T_max = (pi / dq)^2 / 2m the largest kinetic energy of a class's grids and a the
 // largest half-substep, a T_max is the largest eigenvalue of a T.  The preconditioner
 // removes it at the price of one more transform pair per iteration, which pays once
-// a T_max exceeds about 2 (per-class timings of the ragged batch at Suzuki-6, 2.5 a.u.:
-// the plain solver is faster up to a T_max = 0.4 and even at 1.4, the preconditioned
-// one twice as fast at 5.7; the 8th-order batch at 20 a.u., a T_max = 5.0, 1.8x).
+// a T_max exceeds about 1.25 (per-class timings of the ragged batch at Suzuki-6,
+// 2.5 a.u.: the plain solver is 24 % faster at a T_max = 0.35, the preconditioned one
+// 6 % faster at 1.4 and twice as fast at 5.7; the 8th-order batch at 20 a.u.,
+// a T_max = 5.0, 1.8x; the gradient workload at 1.15 ran faster plain).
 // With per-item steps (not read back from the device) an automatic call
 // preconditions every class.
 int resolve_precond(gqd_handle* h, const gqd_solver_opts* o, const GammaTab& gt, double dt, bool item_steps) {

@@ -135,7 +135,7 @@ class SolverOpts:
     literal: bool = False
     verify: bool = False  # end a solve only on a true residual within tol (restart otherwise)
     # right-precondition GMRES by (1 + i a p^2 / 2m)^-1 (1D); "auto": per size class,
-    # where the kinetic stiffness a T_max of the call exceeds 2
+    # where the kinetic stiffness a T_max of the call exceeds 1.25
     precond: Union[bool, str] = False
 
     def c(self) -> _SolverOpts:

@@ -154,7 +154,7 @@ def test_preconditioned_propagation_matches_oracle(gqd, method):
 def test_automatic_preconditioner_takes_each_class_choice(gqd):
     # precond = 'auto' at Suzuki-6, dt = 2.5 a.u. (largest half-substep a = 0.405): the
     # kinetic stiffness a (pi/dq)^2 / 2m of the [3, 16) grids is 0.02, 0.09, 0.35, 1.4 and
-    # 5.7 from N = 256 to 4096, so only the N = 4096 class is preconditioned.  Every item
+    # 5.7 from N = 256 to 4096, so the N = 2048 and 4096 classes are preconditioned.  Every item
     # must equal, bit for bit, its run under the explicit choice of its class (those
     # runs are held to the oracle above), and the byte count must add up per class.
     items = items_for([n for n in SIZES for _ in range(2)], seed=21)
@@ -166,11 +166,11 @@ def test_automatic_preconditioner_takes_each_class_choice(gqd):
                                        gqd.SolverOpts(tol=1e-17, restart=32, precond=pc))
             outs[pc] = prop.unpack(psi)
     for k, it in enumerate(items):
-        want = outs[True][k] if it.n == 4096 else outs[False][k]
+        want = outs[True][k] if it.n >= 2048 else outs[False][k]
         assert np.array_equal(outs["auto"][k], want), f"item {k} (n={it.n})"
     # per-class byte counts: run the two groups separately under their own choice
     parts = 0.0
-    for pc, sel in ((True, [it for it in items if it.n == 4096]), (False, [it for it in items if it.n != 4096])):
+    for pc, sel in ((True, [it for it in items if it.n >= 2048]), (False, [it for it in items if it.n < 2048])):
         with gqd.from_items(sel) as prop:
             psi = prop.pack([it.psi0 for it in sel])
             parts += prop.propagate(psi, "midp", "suzuki", 6, 2.5, 1,
