@@ -1439,8 +1439,8 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
         if constexpr (PC) {
           // Arnoldi step j on X M^-1 (right preconditioning), shifted by s = 1 + i al e:
           // w = z_j + i al H z_j - s v_j, one classical Gram-Schmidt pass over v_0..v_j
-          // with |w|^2 from the same reduction, a second pass when the first keeps less
-          // than kReorthRatio of |w|^2.  X M^-1 = 1 + i al (H - T) M^-1 has no Hermitian
+          // with |w|^2 from the same reduction (its last turn parked in the stash for the
+          // update), a second pass when the first keeps less than kReorthRatio of |w|^2.  X M^-1 = 1 + i al (H - T) M^-1 has no Hermitian
           // structure to exploit.  Unshifted, w lies mostly along v_j (the identity and
           // the potential's mean), the pass cancels most of |w|^2 and the second pass
           // runs on nearly every step; with e the Rayleigh energy of the previous solve
@@ -1460,12 +1460,12 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
                 y.v[s][r] = csub(cadd(z.v[s][r], cmul_is(y.v[s][r], al)), cmul(sft, v.v[s][r]));
           }
           extra_vecs += 1;  // v_j read again for the shift
-          E::template block_dots<E::kStashOff>(basis, y, j + 1, c, c.hcol, true);
+          E::template block_dots<E::kStashFill>(basis, y, j + 1, c, c.hcol, true);
           const double w2 = uniform_d(c.hcol[j + 1].x);
           double hn2 = w2;
           for (int i = 0; i <= j; ++i) hn2 -= cabs2(c.hcol[i]);
           hn2 = uniform_d(hn2);
-          E::template block_axpy<false>(basis, c.hcol, j + 1, y, c);
+          E::template block_axpy<true>(basis, c.hcol, j + 1, y, c);
           // The second pass only serves v_(j+1).  Where it is due, the step is most often
           // the cycle's last (the new direction is small against w as the residual
           // estimate reaches the tolerance), which the one-pass column decides as well:
@@ -1482,11 +1482,11 @@ __global__ void __launch_bounds__(Eng<P>::T) __attribute__((amdgpu_waves_per_eu(
           }
           if (reorth) {
             extra_vecs += 2 * (j + 1);
-            E::template block_dots<E::kStashOff>(basis, y, j + 1, c, c.y, true);
+            E::template block_dots<E::kStashUse>(basis, y, j + 1, c, c.y, true);
             double r2 = uniform_d(c.y[j + 1].x);
             for (int i = 0; i <= j; ++i) r2 -= cabs2(c.y[i]);
             hn2 = uniform_d(r2 > 0.0 ? r2 : 0.0);
-            E::template block_axpy<false>(basis, c.y, j + 1, y, c);
+            E::template block_axpy<true>(basis, c.y, j + 1, y, c);
             // every wave has read the pass's coefficients before the column gains them
             __syncthreads();
             for (int i = threadIdx.x; i <= j; i += T) c.hcol[i] = cadd(c.hcol[i], c.y[i]);
