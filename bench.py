@@ -74,9 +74,9 @@ TOL_ADJ = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "2fc74282d7c941ea3122151c1f79e2c3e0f7db92366a7b79a4f7e22d7b1c9556",
-    "fetch_kib": 168158312.75, "fetch_scale": 2.0,
-    "write_kib": 108957182.875, "write_scale": 1.0,
+    "sources_sha256": "2becb8fcea9726d14f130a7f32716dd87aa57af846d766849a27947cd83ade08",
+    "fetch_kib": 157545079.875, "fetch_scale": 2.0,
+    "write_kib": 108926830.25, "write_scale": 1.0,
     "alg_bytes_same_launch": 587776983040.0,
     "precond": True,
     "summary": "profiles/k_run_2048_sz8_draws1024_precond.md",
