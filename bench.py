@@ -74,10 +74,10 @@ TOL_ADJ = 1e-14
 # well.  Valid only for the device sources it was taken on: reported as null once they
 # change.
 TRAFFIC = {
-    "sources_sha256": "2becb8fcea9726d14f130a7f32716dd87aa57af846d766849a27947cd83ade08",
-    "fetch_kib": 157545079.875, "fetch_scale": 2.0,
-    "write_kib": 108926830.25, "write_scale": 1.0,
-    "alg_bytes_same_launch": 587776983040.0,
+    "sources_sha256": "333defb93d6eefbbe0ce562759214722a212ad56242de9fc71bc3be368adb126",
+    "fetch_kib": 154135353.4375, "fetch_scale": 2.0,
+    "write_kib": 109018168.0, "write_scale": 1.0,
+    "alg_bytes_same_launch": 587887935488.0,
     "precond": True,
     "summary": "profiles/k_run_2048_sz8_draws1024_precond.md",
 }
