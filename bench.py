@@ -324,9 +324,10 @@ def adjoint_leg(gqd, inputs, dev, batch: int, nsteps: int) -> dict:
     q = ag.grid(1024, items[0].qmin, items[0].qmax, dev)
     P = {k: torch.tensor([it.params[k] for it in items], dtype=torch.float64, device=dev, requires_grad=True)
          for k in ["q0", "p0", "width", "amp", "center"]}
-    # plain GMRES: at N = 1024 and 4 a.u. the kinetic part is not stiff (a p_max^2 / 2m
-    # about 1), and the preconditioner's extra transform pair per iteration costs more
-    # than the one or two iterations it saves (68.7 against 86.8 gradients/s)
+    # plain GMRES: at N = 1024 and 4 a.u. the kinetic part is not stiff (a T_max = 1.15),
+    # and over the 1000 steps the preconditioner's extra transform pair per iteration
+    # costs more than the 3 % of iterations it saves (78.9 against 86.7 gradients/s; over
+    # the first 200 steps, where it saves 13 %, it is the faster, 364 against 311)
     opts = gqd.SolverOpts(tol=TOL_ADJ, restart=32)
     with gqd.from_items(items, device=dev) as prop:
         def gradient(steps):
